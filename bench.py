@@ -1,0 +1,167 @@
+"""Benchmark: SSCA at N = 2^20, Np = 64 on one seeded QPSK signal (the paper's large-window workload).
+
+One step = one full SSCA of the signal: Stage 1 (channelizer + channel-data product + M1-point DFT +
+rotation) and Stage 2 (M2-point DFT), exactly the kernels scd_ssca runs, called as the two ABI stages so that
+HIP events on the launch stream time each kernel inside the timed region.
+
+Prints one JSON line. `value` is SCD points/s = Np*N / (seconds per step) with x, window and output already
+resident in HBM. `roofline` reports the dominant kernel's algorithmic HBM bytes per launch over its average
+event-timed duration against the 8 TB/s HBM peak. `cpu_baseline` times the FP64 oracle on this host
+(single-threaded numpy) over all 64 strips of the same signal, which also gives the error of every GPU form
+against it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SCD pts/s, SSCA N=2^20 N'=64: FP32 vs split-BF16 vs learned strips"
+PAPER_PTS_PER_S = 2 ** 26 / 0.114  # VCK5000, 114 ms per SSCA estimate at N=2^20, N_P=64 (Table III)
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("scd_device.h", "ssca_fp32.hip")
+
+
+def source_digest(files=KERNEL_SOURCES) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2506_18003_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on this source."""
+    path = os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("source_digest") != digest:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--forms", default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the SSCA strips would shard over GPUs by channel, but this "
+              "build runs and reports a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_18003_amd as scd
+    from synth import workloads as W
+
+    dev = torch.device("cuda:0")
+    c = W.cfg3()
+    N, Np = c["ssca"]["N"], c["ssca"]["Np"]
+    x64 = c["x"].astype(np.complex64)
+    w32 = c["ssca"]["win"].astype(np.float32)
+    x = torch.from_numpy(x64).to(dev)
+    win = torch.from_numpy(w32).to(dev)
+    inter = torch.empty(Np * N, dtype=torch.complex64, device=dev)
+    out = torch.empty(Np, N, dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = {}
+    for form in forms:
+        for _ in range(args.warmup):
+            scd.ssca_stage1(x, Np, inter, win=win, precision=form)
+            scd.ssca_stage2(inter, N, Np, out)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            scd.ssca_stage1(x, Np, inter, win=win, precision=form)
+            ev[i][1].record(stream)
+            scd.ssca_stage2(inter, N, Np, out)
+            ev[i][2].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p1 = sorted(e[0].elapsed_time(e[1]) for e in ev)
+        p2 = sorted(e[1].elapsed_time(e[2]) for e in ev)
+        tot = sorted(e[0].elapsed_time(e[2]) for e in ev)
+        ms = (t1 - t0) * 1e3 / args.steps
+        results[form] = dict(ms_per_step=ms, pass1_ms=float(np.mean(p1)), pass2_ms=float(np.mean(p2)),
+                             step_ms_p10=tot[len(tot) // 10], step_ms_p50=tot[len(tot) // 2],
+                             step_ms_p90=tot[(9 * len(tot)) // 10], out=out.cpu().numpy())
+
+    # Algorithmic HBM bytes per launch (one signal): pass 1 reads x and writes the intermediate; pass 2 reads
+    # and writes Np*N complex values.
+    b1 = 8 * N + 8 * Np * N
+    b2 = 2 * 8 * Np * N
+    main_form = forms[0]
+    r = results[main_form]
+    digest = source_digest()
+    kern = {"ssca_pass1": (b1, r["pass1_ms"]), "ssca_pass2": (b2, r["pass2_ms"])}
+    dom = max(kern, key=lambda k: kern[k][1])
+    dbytes, dms = kern[dom]
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, digest),
+            "algorithmic_bytes": dbytes, "avg_ms": round(dms, 5),
+            "per_kernel": {k: {"avg_ms": round(v[1], 5), "algorithmic_bytes": v[0],
+                               "GB/s": round(v[0] / (v[1] * 1e-3) / 1e9, 1)} for k, v in kern.items()},
+            "B_2p_frac": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "source_digest": digest}
+
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        from oracle import scd_oracle as O
+
+        xf = x64.astype(np.complex128)
+        wf = w32.astype(np.float64)
+        t0 = time.perf_counter()
+        ref = np.stack([O.ssca_strip(xf, Np, wf, k) for k in range(Np)])
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(Np * N / dt, 1), "unit": "SCD pts/s", "cores": 1, "kind": "oracle",
+               "sample": f"all {Np} strips of the same N=2^20 signal (FP64 numpy oracle: per-strip FIR "
+                         f"channelizer + numpy.fft), {dt:.1f} s single-threaded"}
+        peak = np.abs(ref).max()
+        for form, rr in results.items():
+            errs[form] = float(np.abs(rr["out"] - ref).max() / peak)
+
+    value = Np * N / (r["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "SCD pts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": round(value / PAPER_PTS_PER_S, 2),
+        "vs_baseline_note": "paper's VCK5000 SSCA, 114 ms per estimate at this workload (other hardware)",
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "SSCA N=2^20 Np=64, one QPSK signal (complex carrier 0.1, 8 samples/symbol, "
+                               "5 dB AWGN), Hamming window", "N": N, "Np": Np, "form": main_form},
+        "roofline": roof, "cpu_baseline": cpu,
+        "forms": {f: {"pts_per_s": round(Np * N / (rr["ms_per_step"] * 1e-3), 1),
+                      "ms_per_step": round(rr["ms_per_step"], 5), "p10_ms": round(rr["step_ms_p10"], 5),
+                      "p50_ms": round(rr["step_ms_p50"], 5), "p90_ms": round(rr["step_ms_p90"], 5),
+                      "pass1_ms": round(rr["pass1_ms"], 5), "pass2_ms": round(rr["pass2_ms"], 5),
+                      "max_err_vs_oracle": errs.get(f)} for f, rr in results.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

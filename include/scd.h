@@ -1,0 +1,172 @@
+/*
+ * scd.h - C ABI of a spectral correlation density (SCD) library for AMD Instinct MI355X (gfx950).
+ *
+ * Two estimators of the SCD are provided (arXiv 2506.18003, Sec. II):
+ *   FAM   the FFT accumulation method, Eq. (3)-(5);
+ *   SSCA  the strip spectral correlation analyser, Eq. (6)-(7), computed through the decomposed N-point
+ *         DFT of Sec. III-B (Eq. (10)-(16)).
+ *
+ * Conventions shared by every entry point
+ *   - Complex arrays are interleaved float pairs (re, im), i.e. complex64; `n` complex values take 2n floats.
+ *   - x, win and out are DEVICE pointers (hipMalloc'd, managed, or hipHostMalloc'd memory the GPU can read),
+ *     contiguous, 8-byte aligned. The caller owns them; the library never retains them after a call.
+ *   - Calls enqueue kernels on a HIP stream and return without waiting: on the stream in scd_opts, else
+ *     on the stream given to scd_set_stream (default: the null stream). Only the first call for a new
+ *     (size, channel count) pair synchronises, while it generates its FP64 tables.
+ *   - Frames are centred as in Eq. (3): frame p covers samples pL - d + j, j = 0..Np-1, d = Np/2 - 1, and
+ *     win[j] multiplies sample j of the frame. Samples outside the signal are zero.
+ *   - The down-conversion factor is Eq. (3)'s exp(-i 2 pi k p L / Np) with the integer exponent reduced
+ *     mod Np. Channel k and bin q are in natural DFT order (k, q >= 0). No normalisation is applied
+ *     (g = g_d = 1).
+ *   - Return 0 (SCD_OK) on success, or a negative SCD_ERR_* code; scd_last_error() then gives a message.
+ *     Argument errors are detected before any GPU work is enqueued. On error, out is unspecified and x and
+ *     win are never written. Nothing is printed and no C++ exception crosses the ABI.
+ *   - The library's own device memory (FP64-generated tables, the SSCA intermediate) is allocated on
+ *     first use per device and released by scd_shutdown().
+ */
+#ifndef SCD_H
+#define SCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SCD_OK 0
+#define SCD_ERR_NULL (-1)        /* a required pointer is NULL                                         */
+#define SCD_ERR_SIZE (-2)        /* a size is not a power of two, out of range, or inconsistent        */
+#define SCD_ERR_ALIAS (-3)       /* out overlaps x, win or the workspace                                */
+#define SCD_ERR_NOMEM (-4)       /* device allocation failed or the caller's workspace is too small     */
+#define SCD_ERR_HIP (-5)         /* a HIP runtime call or kernel launch failed                          */
+#define SCD_ERR_MODEL (-6)       /* invalid selector model                                              */
+#define SCD_ERR_UNSUPPORTED (-7) /* valid arguments, but this precision/size combination is not built   */
+#define SCD_ERR_PTR (-8)         /* a pointer is not device-accessible memory, or its allocation is
+                                    smaller than the array it must hold                                 */
+
+/* Arithmetic of the channelizer DFT (Eq. (3)). Everything after the channelizer is FP32.
+ *   SCD_FP32        FP32 throughout.
+ *   SCD_SPLIT_BF16  channelizer as a DFT-GEMM on MFMA with bf16 hi/lo split operands (3 products), FP32
+ *                   accumulation.
+ *   SCD_SPLIT_FP16  the same with fp16 hi/lo operands.
+ *   SCD_BF16        a single bf16 product (no split), FP32 accumulation: an accuracy ablation.
+ *   SCD_FP16        a single fp16 product (no split), FP32 accumulation: an accuracy ablation. */
+typedef enum scd_precision {
+  SCD_FP32 = 0,
+  SCD_SPLIT_BF16 = 1,
+  SCD_SPLIT_FP16 = 2,
+  SCD_BF16 = 3,
+  SCD_FP16 = 4
+} scd_precision;
+
+/* Options of the _ex entry points. Zero-initialise, then set what you need.
+ *   precision        an scd_precision value (FP32 if 0)
+ *   batch            number of signals (0 or 1 = one signal); signals and outputs are laid out at the
+ *                    strides below
+ *   x_stride         complex elements between consecutive signals of x (0 = the signal length)
+ *   out_stride       complex elements between consecutive outputs (0 = the output size)
+ *   stream           hipStream_t to enqueue on (NULL = the stream given to scd_set_stream)
+ *   workspace        device scratch for the SSCA intermediate or FAM's X_T (NULL = library-owned); must not
+ *                    overlap x, win or out; its contents are undefined after the call
+ *   workspace_bytes  size of workspace; see scd_ssca_workspace_size / scd_fam_workspace_size */
+typedef struct scd_opts {
+  int precision;
+  int batch;
+  int64_t x_stride;
+  int64_t out_stride;
+  void* stream;
+  void* workspace;
+  size_t workspace_bytes;
+} scd_opts;
+
+/*
+ * scd_ssca - SSCA estimate of one signal (Sec. II-C, Eq. (6)-(7); Sec. III-B, Eq. (10)-(16)).
+ *
+ *   S[k][q] = sum_{n=0}^{N-1} X_T[n][k] conj(x[n]) exp(-i 2 pi n q / N),   k in [0,Np), q in [0,N),
+ *   X_T[n][k] = exp(-i 2 pi ((k n) mod Np) / Np) * sum_{j<Np} win[j] x[n - d + j] exp(-i 2 pi k j / Np).
+ *
+ * Cell [k][q] estimates the SCD at alpha = f_k + q_c/N, f = (f_k - q_c/N)/2 (f_s = 1), with k_c, q_c the
+ * signed indices ((k + Np/2) mod Np) - Np/2 and ((q + N/2) mod N) - N/2 and f_k = k_c/Np.
+ *
+ *   x    device, N complex values
+ *   N    SSCA window = signal length, a power of two in [2^10, 2^20]
+ *   Np   channel count, a power of two in [16, 256], Np <= N
+ *   win  device, Np floats
+ *   out  device, Np*N complex values, row-major [Np][N]
+ * Errors: SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_ALIAS, SCD_ERR_PTR, SCD_ERR_NOMEM, SCD_ERR_HIP.
+ * Uses a library-owned intermediate of 8*Np*N bytes when N > 1024. That buffer is shared by every call
+ * on the device that passes no workspace: such calls must not run concurrently on different streams.
+ */
+int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out);
+
+/* scd_ssca with options: precision, batching (x: [batch] signals at x_stride, out: [batch][Np][N] at
+ * out_stride), stream and caller workspace. A caller workspace smaller than one signal's intermediate gives
+ * SCD_ERR_NOMEM; a smaller batch chunk is used when it holds fewer than `batch` intermediates. Split
+ * precisions require Np <= 128 (SCD_ERR_UNSUPPORTED otherwise). */
+int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts);
+
+/*
+ * scd_ssca_stage1_ex / scd_ssca_stage2_ex - the two stages of SSCA_2DFFT (Sec. III-B, Eq. (14)-(16)) as
+ * separate calls, so a caller can time, pipeline or interleave them. scd_ssca_ex runs exactly stage 1
+ * followed by stage 2 through a library-owned intermediate.
+ *
+ * With N = M1*M2, M1 = 1024, M2 = N/1024, stage 1 generates the channel-data product X_g(m1*M2 + m2, k)
+ * (Eq. (11)-(13)), takes the M1-point DFT over m1 and multiplies by the rotation factor
+ * exp(-i 2 pi m2 m1' / N) (Eq. (15)); it writes S_s1(m1', m2, k) to `inter` in the blocked layout
+ * inter[k][m1'/16][m2][m1' mod 16] (Np*N complex values per signal). Stage 2 takes the M2-point DFT over m2
+ * (Eq. (16)) and writes S[k][q], q = m1' + M1*m2', to out ([Np][N]).
+ *   stage 1: x (N complex per signal, opts->x_stride), win, inter (opts->out_stride, default Np*N)
+ *   stage 2: inter (opts->x_stride, default Np*N), out (opts->out_stride, default Np*N); win is not used
+ * With N == 1024 the intermediate layout equals the output layout and stage 2 only copies (nothing when
+ * inter == out). Precision (stage 1 only) as in scd_ssca_ex. Errors as scd_ssca_ex.
+ */
+int scd_ssca_stage1_ex(const float* x, int64_t N, int Np, const float* win, float* inter, const scd_opts* opts);
+int scd_ssca_stage2_ex(const float* inter, int64_t N, int Np, float* out, const scd_opts* opts);
+
+/*
+ * scd_fam - FAM estimate of one signal (Sec. II-B, Eq. (3)-(5)).
+ *
+ *   S[k][l][q] = sum_{p=0}^{P-1} X_T[p][k] conj(X_T[p][l]) exp(-i 2 pi p q / P),
+ *   X_T[p][k]  = exp(-i 2 pi ((k p L) mod Np) / Np) * sum_{j<Np} win[j] x[pL - d + j] exp(-i 2 pi k j / Np),
+ * over the first N = P*L samples. Cell [k][l][q] estimates the SCD at f = (f_k + f_l)/2,
+ * alpha = f_k - f_l + q_c/(P L); bins with |q_c| < P L / Np are inside the pair's channel overlap.
+ *
+ *   x    device, P*L complex values
+ *   Np   channel count, a power of two in [16, 256]
+ *   L    hop between frames, a power of two in [1, Np] (the paper uses Np/4)
+ *   P    frame count, a power of two in [4, 1024], P*L <= 2^16
+ *   win  device, Np floats
+ *   out  device, Np*Np*P complex values, row-major [Np][Np][P] (k unconjugated, l conjugated)
+ * Errors: SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_ALIAS, SCD_ERR_PTR, SCD_ERR_NOMEM, SCD_ERR_HIP.
+ */
+int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out);
+
+/* scd_fam with options (batch, strides, stream, workspace for X_T). Only SCD_FP32 is supported. */
+int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
+
+/* Bytes of workspace scd_ssca_ex needs for `batch` signals (0 when N == 1024). Errors: SCD_ERR_NULL,
+ * SCD_ERR_SIZE. */
+int scd_ssca_workspace_size(int64_t N, int Np, int batch, size_t* bytes);
+
+/* Bytes of workspace scd_fam_ex needs for `batch` signals. Errors: SCD_ERR_NULL, SCD_ERR_SIZE. */
+int scd_fam_workspace_size(int Np, int L, int P, int batch, size_t* bytes);
+
+/* Set the default stream (a hipStream_t, NULL = null stream) used when scd_opts.stream is NULL. */
+int scd_set_stream(void* stream);
+
+/* The message of the calling thread's last failed call ("" if none). Valid until its next call. */
+const char* scd_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int scd_version(void);
+
+/* Wait for the library's work, then free its tables and workspaces on every device. Safe to call twice. */
+void scd_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCD_H */

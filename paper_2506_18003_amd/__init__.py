@@ -1,0 +1,197 @@
+"""Spectral correlation density (FAM and SSCA) on AMD MI355X.
+
+Thin Python layer over the C ABI in include/scd.h. torch supplies device memory and the current stream;
+every numerical step runs in the library's HIP kernels (``libscd.so``), and the calls fail loudly if that
+library is missing.
+
+    S = ssca(x, Np)                 # x: complex64 CUDA tensor [N] or [B, N]  ->  [Np, N] or [B, Np, N]
+    S = fam(x, Np, L, P)            # x: [P*L] or [B, P*L]                      ->  [Np, Np, P] or [B, Np, Np, P]
+    f, alpha = ssca_coords(Np, N)   # the (f, alpha) of each SSCA cell
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import PRECISIONS, ScdError  # noqa: F401
+
+__all__ = ["ssca", "ssca_stage1", "ssca_stage2", "fam", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+           "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
+
+_win_cache: dict = {}
+
+
+def hamming(n: int) -> np.ndarray:
+    """Symmetric Hamming window 0.54 - 0.46 cos(2 pi j / (n - 1)), float64."""
+    j = np.arange(n)
+    return 0.54 - 0.46 * np.cos(2.0 * np.pi * j / (n - 1))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _window(win, Np, device):
+    torch = _torch()
+    if win is None:
+        key = (Np, str(device))
+        w = _win_cache.get(key)
+        if w is None:
+            w = torch.tensor(hamming(Np), dtype=torch.float32, device=device)
+            _win_cache[key] = w
+        return w
+    if not isinstance(win, torch.Tensor):
+        win = torch.tensor(np.asarray(win), dtype=torch.float32, device=device)
+    if win.dtype != torch.float32 or win.device != device or not win.is_contiguous() or win.numel() != Np:
+        raise ValueError(f"win must be a contiguous float32 tensor of {Np} values on {device}")
+    return win
+
+
+def _check_x(x):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex64 or not x.is_cuda:
+        raise TypeError("x must be a complex64 CUDA tensor")
+    if x.dim() not in (1, 2):
+        raise ValueError("x must be [N] or [B, N]")
+    if x.stride(-1) != 1:
+        raise ValueError("x must be contiguous along its last axis")
+
+
+def _opts(x, precision, batch, x_stride, out_stride, workspace):
+    torch = _torch()
+    o = _lib.ScdOpts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.batch = batch
+    o.x_stride = x_stride
+    o.out_stride = out_stride
+    o.stream = torch.cuda.current_stream(x.device).cuda_stream
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous CUDA tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+def ssca(x, Np: int, win=None, precision="fp32", out=None, workspace=None):
+    """SSCA estimate S[k][q] (k < Np, q < N) of each signal in x; see scd_ssca in include/scd.h."""
+    torch = _torch()
+    _check_x(x)
+    N = x.shape[-1]
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, N) if x.dim() == 1 else (B, Np, N)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, precision, B, xs, Np * N, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_ex(x.data_ptr(), N, Np, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def ssca_stage1(x, Np: int, inter, win=None, precision="fp32"):
+    """Stage 1 of SSCA_2DFFT into `inter` (complex64, Np*N elements per signal); see scd_ssca_stage1_ex."""
+    torch = _torch()
+    _check_x(x)
+    N = x.shape[-1]
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    if inter.dtype != torch.complex64 or not inter.is_contiguous() or inter.numel() != B * Np * N:
+        raise ValueError("inter must be a contiguous complex64 tensor of batch*Np*N elements")
+    o = _opts(x, precision, B, x.stride(0) if x.dim() == 2 else 0, Np * N, None)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_stage1_ex(x.data_ptr(), N, Np, w.data_ptr(), inter.data_ptr(),
+                                                 ctypes.byref(o)))
+    return inter
+
+
+def ssca_stage2(inter, N: int, Np: int, out):
+    """Stage 2 of SSCA_2DFFT from `inter` into out ([.., Np, N] complex64); see scd_ssca_stage2_ex."""
+    torch = _torch()
+    B = inter.numel() // (Np * N)
+    if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() != B * Np * N:
+        raise ValueError("out must be a contiguous complex64 tensor of batch*Np*N elements")
+    o = _opts(inter, "fp32", B, Np * N, Np * N, None)
+    with torch.cuda.device(inter.device):
+        _lib.check(_lib.lib().scd_ssca_stage2_ex(inter.data_ptr(), N, Np, out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def fam(x, Np: int, L: int | None = None, P: int | None = None, win=None, out=None, workspace=None):
+    """FAM estimate S[k][l][q] of each signal in x (default L = Np/4, P = len/L); see scd_fam."""
+    torch = _torch()
+    _check_x(x)
+    if L is None:
+        L = Np // 4
+    if P is None:
+        P = x.shape[-1] // L
+    if x.shape[-1] < P * L:
+        raise ValueError(f"x has {x.shape[-1]} samples, FAM needs P*L = {P * L}")
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, Np, P) if x.dim() == 1 else (B, Np, Np, P)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, "fp32", B, xs, Np * Np * P, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_fam_ex(x.data_ptr(), Np, L, P, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def ssca_workspace_size(N: int, Np: int, batch: int = 1) -> int:
+    v = ctypes.c_size_t()
+    _lib.check(_lib.lib().scd_ssca_workspace_size(N, Np, batch, ctypes.byref(v)))
+    return v.value
+
+
+def fam_workspace_size(Np: int, L: int, P: int, batch: int = 1) -> int:
+    v = ctypes.c_size_t()
+    _lib.check(_lib.lib().scd_fam_workspace_size(Np, L, P, batch, ctypes.byref(v)))
+    return v.value
+
+
+def shutdown() -> None:
+    _lib.lib().scd_shutdown()
+
+
+def version() -> int:
+    return _lib.lib().scd_version()
+
+
+def _signed(n: int) -> np.ndarray:
+    i = np.arange(n)
+    return ((i + n // 2) % n) - n // 2
+
+
+def ssca_coords(Np: int, N: int):
+    """(f, alpha) arrays [Np, N] of the SSCA cells (f_s = 1): alpha = f_k + q_c/N, f = (f_k - q_c/N)/2."""
+    fk = (_signed(Np) / Np)[:, None]
+    qn = (_signed(N) / N)[None, :]
+    return (fk - qn) / 2.0, fk + qn
+
+
+def fam_coords(Np: int, L: int, P: int):
+    """(f, alpha) arrays [Np, Np, P] of the FAM cells: f = (f_k + f_l)/2, alpha = f_k - f_l + q_c/(P L)."""
+    fk = _signed(Np) / Np
+    qa = _signed(P) / (P * L)
+    f = np.broadcast_to(((fk[:, None] + fk[None, :]) / 2.0)[:, :, None], (Np, Np, P))
+    a = (fk[:, None] - fk[None, :])[:, :, None] + qa[None, None, :]
+    return f, a
+
+
+def fam_paper_view(S):
+    """|S|^2 over the central half of the alpha-offset axis (|q_c| < P/4), natural order
+    [0..P/4-1, -P/4..-1]; the bins the paper's FFT2 stage keeps."""
+    torch = _torch()
+    P = S.shape[-1]
+    idx = torch.cat([torch.arange(0, P // 4), torch.arange(P - P // 4, P)]).to(S.device)
+    return S.index_select(-1, idx).abs().square()

@@ -1,0 +1,382 @@
+// C ABI of the SCD library: argument validation, per-device plan cache of FP64-generated tables, workspace
+// management, stream selection and error reporting. All numerical work is in the kernels; this file only
+// checks arguments and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "scd.h"
+#include "scd_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_mu;
+hipStream_t g_stream = nullptr;
+
+struct DevState {
+  std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+std::map<int, DevState> g_dev;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  return fail(SCD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  if (an == 0 || bn == 0) return false;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bn && b0 < a0 + an;
+}
+
+// The GPU may read/write `bytes` starting at p: p is device, managed or pinned-host memory and its
+// allocation extends at least that far.
+int check_device_range(const void* p, size_t bytes, const char* name) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCD_ERR_PTR, "%s is not memory the GPU can access (%s)", name, hipGetErrorString(e));
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeHost &&
+      attr.type != hipMemoryTypeUnified) {
+    return fail(SCD_ERR_PTR, "%s is not memory the GPU can access", name);
+  }
+  if (attr.type == hipMemoryTypeDevice) {
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    if (e == hipSuccess && base != nullptr) {
+      const uintptr_t end = reinterpret_cast<uintptr_t>(base) + size;
+      if (reinterpret_cast<uintptr_t>(p) + bytes > end)
+        return fail(SCD_ERR_PTR, "%s: allocation holds %zu bytes from this pointer, %zu needed", name,
+                    static_cast<size_t>(end - reinterpret_cast<uintptr_t>(p)), bytes);
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return SCD_OK;
+}
+
+// Tables for (transform length n, Np): omega_1024, omega_n^j (j < 1024) and omega_Np. Generated once in FP64
+// on the GPU; creation waits for the generation to finish so any stream may use them afterwards.
+int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, const float2** out) {
+  auto key = std::make_pair(n, Np);
+  auto it = st.plans.find(key);
+  if (it != st.plans.end()) {
+    *out = it->second;
+    return SCD_OK;
+  }
+  float2* t = nullptr;
+  hipError_t e = hipMalloc(&t, sizeof(float2) * scd::kTabSize);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCD_ERR_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
+  }
+  e = scd::launch_gen_roots(t + scd::kTabTw1024, 1024, 1024, s);
+  if (e == hipSuccess) e = scd::launch_gen_roots(t + scd::kTabRotLo, 1024, static_cast<int>(n), s);
+  if (e == hipSuccess) e = scd::launch_gen_roots(t + scd::kTabRoots, Np, Np, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(t);
+    return hip_fail(e, "table generation");
+  }
+  st.plans[key] = t;
+  *out = t;
+  return SCD_OK;
+}
+
+// Library-owned workspace of at least `bytes`, grown on demand.
+int get_work(DevState& st, size_t bytes, void** out) {
+  if (bytes == 0) {
+    *out = nullptr;
+    return SCD_OK;
+  }
+  if (st.work_bytes < bytes) {
+    if (st.work) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
+      (void)hipFree(st.work);
+      st.work = nullptr;
+      st.work_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&st.work, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      st.work = nullptr;
+      return fail(SCD_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    st.work_bytes = bytes;
+  }
+  *out = st.work;
+  return SCD_OK;
+}
+
+int current_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  return SCD_OK;
+}
+
+struct Resolved {
+  int precision = SCD_FP32;
+  int batch = 1;
+  int64_t xs = 0, os = 0;
+  hipStream_t stream = nullptr;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+
+int resolve(const scd_opts* o, int64_t xlen, int64_t olen, Resolved* r) {
+  r->stream = g_stream;
+  r->xs = xlen;
+  r->os = olen;
+  if (!o) return SCD_OK;
+  r->precision = o->precision;
+  r->batch = o->batch <= 0 ? 1 : o->batch;
+  if (o->x_stride < 0 || o->out_stride < 0) return fail(SCD_ERR_SIZE, "negative stride");
+  if (o->x_stride) r->xs = o->x_stride;
+  if (o->out_stride) r->os = o->out_stride;
+  if (r->batch > 1 && (r->xs < xlen || r->os < olen))
+    return fail(SCD_ERR_SIZE, "stride smaller than one signal (x_stride %lld < %lld or out_stride %lld < %lld)",
+                static_cast<long long>(r->xs), static_cast<long long>(xlen), static_cast<long long>(r->os),
+                static_cast<long long>(olen));
+  if (o->stream) r->stream = static_cast<hipStream_t>(o->stream);
+  r->work = o->workspace;
+  r->work_bytes = o->workspace_bytes;
+  if (r->work == nullptr && r->work_bytes != 0) return fail(SCD_ERR_NULL, "workspace_bytes set without workspace");
+  return SCD_OK;
+}
+
+size_t span_bytes(int batch, int64_t stride, int64_t len) {
+  return 8u * static_cast<size_t>(static_cast<int64_t>(batch - 1) * stride + len);
+}
+
+}  // namespace
+
+extern "C" {
+
+int scd_version(void) { return (1 << 16) | 0; }
+
+const char* scd_last_error(void) { return g_err.c_str(); }
+
+int scd_set_stream(void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_stream = static_cast<hipStream_t>(stream);
+  return SCD_OK;
+}
+
+int scd_ssca_workspace_size(int64_t N, int Np, int batch, size_t* bytes) {
+  if (!bytes) return fail(SCD_ERR_NULL, "bytes is NULL");
+  if (!is_pow2(N) || N < 1024 || N > (1 << 20)) return fail(SCD_ERR_SIZE, "N must be a power of two in [2^10, 2^20]");
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
+  if (batch < 1) batch = 1;
+  *bytes = (N == 1024) ? 0 : 8u * static_cast<size_t>(Np) * static_cast<size_t>(N) * static_cast<size_t>(batch);
+  return SCD_OK;
+}
+
+int scd_fam_workspace_size(int Np, int L, int P, int batch, size_t* bytes) {
+  if (!bytes) return fail(SCD_ERR_NULL, "bytes is NULL");
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
+  if (!is_pow2(L) || L > Np) return fail(SCD_ERR_SIZE, "L must be a power of two in [1, Np]");
+  if (!is_pow2(P) || P < 4 || P > 1024) return fail(SCD_ERR_SIZE, "P must be a power of two in [4, 1024]");
+  if (batch < 1) batch = 1;
+  *bytes = 8u * static_cast<size_t>(Np) * static_cast<size_t>(P) * static_cast<size_t>(batch);
+  return SCD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+enum class SscaPart { kWhole, kStage1, kStage2 };
+
+// Shared validation and dispatch of the SSCA entry points. For kStage1 `in` is x and `dst` the intermediate;
+// for kStage2 `in` is the intermediate and `dst` the output (win unused); for kWhole `in` is x and `dst` out.
+int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* win, float* dst,
+                const scd_opts* opts) {
+  const bool need_win = part != SscaPart::kStage2;
+  if (!in || !dst || (need_win && !win)) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
+  if (!is_pow2(N) || N < 1024 || N > (1 << 20))
+    return fail(SCD_ERR_SIZE, "N = %lld must be a power of two in [2^10, 2^20]", static_cast<long long>(N));
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  const int64_t grid = static_cast<int64_t>(Np) * N;
+  const int64_t inlen = (part == SscaPart::kStage2) ? grid : N;
+  Resolved r;
+  int rc = resolve(opts, inlen, grid, &r);
+  if (rc) return rc;
+  if (r.precision < SCD_FP32 || r.precision > SCD_FP16) return fail(SCD_ERR_SIZE, "unknown precision %d", r.precision);
+  if (r.precision != SCD_FP32 && part != SscaPart::kStage2)
+    return fail(SCD_ERR_UNSUPPORTED, "precision %d is not available in this build", r.precision);
+  const size_t ib = span_bytes(r.batch, r.xs, inlen);
+  const size_t ob = span_bytes(r.batch, r.os, grid);
+  const size_t wb = need_win ? 4u * static_cast<size_t>(Np) : 0;
+  if (overlaps(dst, ob, in, ib) || overlaps(dst, ob, win, wb)) return fail(SCD_ERR_ALIAS, "output overlaps an input");
+  const size_t per = (part == SscaPart::kWhole && N > 1024) ? 8u * static_cast<size_t>(grid) : 0;
+  if (part == SscaPart::kWhole && r.work) {
+    if (overlaps(r.work, r.work_bytes, in, ib) || overlaps(r.work, r.work_bytes, dst, ob) ||
+        overlaps(r.work, r.work_bytes, win, wb))
+      return fail(SCD_ERR_ALIAS, "workspace overlaps x, win or out");
+    if (per > 0 && r.work_bytes < per)
+      return fail(SCD_ERR_NOMEM, "workspace of %zu bytes is smaller than one intermediate (%zu)", r.work_bytes, per);
+  }
+
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = check_device_range(in, ib, part == SscaPart::kStage2 ? "intermediate" : "x"))) return rc;
+  if (need_win && (rc = check_device_range(win, wb, "win"))) return rc;
+  if ((rc = check_device_range(dst, ob, part == SscaPart::kStage1 ? "intermediate" : "out"))) return rc;
+  if (part == SscaPart::kWhole && r.work && (rc = check_device_range(r.work, r.work_bytes, "workspace"))) return rc;
+  int dev;
+  if ((rc = current_device(&dev))) return rc;
+  DevState& st = g_dev[dev];
+  const float2* tabs;
+  if ((rc = get_tables(st, N, Np, r.stream, &tabs))) return rc;
+  const float2* ic = reinterpret_cast<const float2*>(in);
+  float2* oc = reinterpret_cast<float2*>(dst);
+  const int n = static_cast<int>(N);
+  hipError_t e = hipSuccess;
+  if (part == SscaPart::kStage1) {
+    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, oc, r.batch, r.xs, r.os, r.stream);
+  } else if (part == SscaPart::kStage2) {
+    if (N == 1024) {
+      // The Stage 1 output already is the result; copy it if the caller asked for another buffer.
+      for (int b = 0; b < r.batch && e == hipSuccess && ic != oc; ++b)
+        e = hipMemcpyAsync(oc + b * r.os, ic + b * r.xs, 8u * static_cast<size_t>(grid), hipMemcpyDeviceToDevice,
+                           r.stream);
+    } else {
+      e = scd::launch_ssca_pass2(ic, n, Np, tabs, oc, r.batch, r.xs, r.os, r.stream);
+    }
+  } else if (per == 0) {
+    // N == 1024: the Stage 1 output is the final result.
+    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, oc, r.batch, r.xs, r.os, r.stream);
+  } else {
+    int chunk = r.batch;
+    void* work = r.work;
+    if (work) {
+      chunk = static_cast<int>(std::min<size_t>(r.batch, r.work_bytes / per));
+    } else if ((rc = get_work(st, per * r.batch, &work))) {
+      return rc;
+    }
+    float2* T = static_cast<float2*>(work);
+    for (int b0 = 0; b0 < r.batch && e == hipSuccess; b0 += chunk) {
+      const int nb = std::min(chunk, r.batch - b0);
+      e = scd::launch_ssca_pass1_fp32(ic + b0 * r.xs, n, Np, win, tabs, T, nb, r.xs, grid, r.stream);
+      if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc + b0 * r.os, nb, grid, r.os, r.stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "SSCA launch");
+  return SCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts) {
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts);
+}
+
+int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out) {
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, nullptr);
+}
+
+int scd_ssca_stage1_ex(const float* x, int64_t N, int Np, const float* win, float* inter, const scd_opts* opts) {
+  return ssca_common(SscaPart::kStage1, x, N, Np, win, inter, opts);
+}
+
+int scd_ssca_stage2_ex(const float* inter, int64_t N, int Np, float* out, const scd_opts* opts) {
+  return ssca_common(SscaPart::kStage2, inter, N, Np, nullptr, out, opts);
+}
+
+int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts) {
+  if (!x || !win || !out) return fail(SCD_ERR_NULL, "x, win and out must be non-NULL");
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  if (!is_pow2(L) || L > Np) return fail(SCD_ERR_SIZE, "L = %d must be a power of two in [1, Np]", L);
+  if (!is_pow2(P) || P < 4 || P > 1024) return fail(SCD_ERR_SIZE, "P = %d must be a power of two in [4, 1024]", P);
+  if (static_cast<int64_t>(P) * L > (1 << 16)) return fail(SCD_ERR_SIZE, "P*L must be at most 2^16");
+  const int64_t n = static_cast<int64_t>(P) * L;
+  const int64_t olen = static_cast<int64_t>(Np) * Np * P;
+  Resolved r;
+  int rc = resolve(opts, n, olen, &r);
+  if (rc) return rc;
+  if (r.precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "FAM is FP32 only");
+  const size_t xb = span_bytes(r.batch, r.xs, n);
+  const size_t ob = span_bytes(r.batch, r.os, olen);
+  const size_t wb = 4u * static_cast<size_t>(Np);
+  if (overlaps(out, ob, x, xb) || overlaps(out, ob, win, wb)) return fail(SCD_ERR_ALIAS, "out overlaps x or win");
+  const size_t per = 8u * static_cast<size_t>(Np) * static_cast<size_t>(P);
+  if (r.work && (overlaps(r.work, r.work_bytes, x, xb) || overlaps(r.work, r.work_bytes, out, ob) ||
+                 overlaps(r.work, r.work_bytes, win, wb)))
+    return fail(SCD_ERR_ALIAS, "workspace overlaps x, win or out");
+  if (r.work && r.work_bytes < per)
+    return fail(SCD_ERR_NOMEM, "workspace of %zu bytes is smaller than one X_T (%zu)", r.work_bytes, per);
+
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = check_device_range(x, xb, "x"))) return rc;
+  if ((rc = check_device_range(win, wb, "win"))) return rc;
+  if ((rc = check_device_range(out, ob, "out"))) return rc;
+  if (r.work && (rc = check_device_range(r.work, r.work_bytes, "workspace"))) return rc;
+  int dev;
+  if ((rc = current_device(&dev))) return rc;
+  DevState& st = g_dev[dev];
+  const float2* tabs;
+  if ((rc = get_tables(st, 1024, Np, r.stream, &tabs))) return rc;
+  int chunk = r.batch;
+  void* work = r.work;
+  if (work) chunk = static_cast<int>(std::min<size_t>(r.batch, r.work_bytes / per));
+  else if ((rc = get_work(st, per * r.batch, &work))) return rc;
+  const float2* xc = reinterpret_cast<const float2*>(x);
+  float2* oc = reinterpret_cast<float2*>(out);
+  for (int b0 = 0; b0 < r.batch; b0 += chunk) {
+    const int nb = std::min(chunk, r.batch - b0);
+    hipError_t e = scd::launch_fam_fp32(xc + b0 * r.xs, Np, L, P, win, tabs, static_cast<float2*>(work),
+                                        oc + b0 * r.os, nb, r.xs, r.os, r.stream);
+    if (e != hipSuccess) return hip_fail(e, "FAM launch");
+  }
+  return SCD_OK;
+}
+
+int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out) {
+  return scd_fam_ex(x, Np, L, P, win, out, nullptr);
+}
+
+void scd_shutdown(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_dev.empty()) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : g_dev) {
+    (void)hipSetDevice(kv.first);
+    (void)hipDeviceSynchronize();
+    for (auto& p : kv.second.plans) (void)hipFree(p.second);
+    if (kv.second.work) (void)hipFree(kv.second.work);
+  }
+  (void)hipSetDevice(cur);
+  g_dev.clear();
+  (void)hipGetLastError();
+}
+
+}  // extern "C"

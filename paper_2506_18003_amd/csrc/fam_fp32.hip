@@ -1,0 +1,126 @@
+// FFT accumulation method (Sec. II-B, Eq. (3)-(5)) in FP32.
+//
+// fam_chan: the channelizer of Eq. (3) with hop L over P frames. A workgroup loads F = 4096/Np centred,
+//   windowed frames into LDS (zero outside [0, P*L)), takes their Np-point DFTs, applies the down-conversion
+//   omega_Np^{(k p L) mod Np} and stores X_T channel-major, xt[k][p], so the pair kernel reads rows.
+//   X_T is at most 256 x 1024 complex (2 MiB) and stays in L2.
+// fam_pair: for channel k and a tile of 16 channels l, forms z[p] = X_T[p][k] conj(X_T[p][l]) (the conjugate
+//   multiplication of Eq. (5)) while loading, takes the P-point DFT of the 16 products in LDS and stores
+//   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic).
+#include <type_traits>
+
+#include "scd_device.h"
+#include "scd_launch.h"
+
+namespace scd {
+
+namespace {
+
+constexpr int kChanThreads = 256;
+constexpr int kPairThreads = 256;
+constexpr int kLT = 16;  // channels l per pair workgroup
+
+template <int NP>
+__global__ __launch_bounds__(kChanThreads) void fam_chan_fp32(const float2* __restrict__ x, int L, int P,
+                                                             const float* __restrict__ win,
+                                                             const float2* __restrict__ tabs,
+                                                             float2* __restrict__ xt, int64_t xbs,
+                                                             int64_t xtbs) {
+  constexpr int F = 4096 / NP;
+  constexpr int D = NP / 2 - 1;
+  __shared__ float2 buf[F * NP];
+  __shared__ float2 tw[1024];
+  __shared__ float2 rt[NP];
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.x * F;
+  const int len = P * L;
+  x += blockIdx.y * xbs;
+  xt += blockIdx.y * xtbs;
+  for (int i = tid; i < 1024; i += kChanThreads) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < NP; i += kChanThreads) rt[i] = tabs[kTabRoots + i];
+  for (int e = tid; e < F * NP; e += kChanThreads) {
+    const int f = e / NP, j = e % NP;
+    const int p = p0 + f;
+    const int idx = p * L - D + j;
+    float2 v = make_float2(0.f, 0.f);
+    if (p < P && static_cast<unsigned>(idx) < static_cast<unsigned>(len)) v = cscale(x[idx], win[j]);
+    buf[e] = v;
+  }
+  __syncthreads();
+  auto st = [&](int f, int k, float2 v) {
+    const int p = p0 + f;
+    if (p < P) xt[static_cast<int64_t>(k) * P + p] = cmul(v, rt[(k * p * L) & (NP - 1)]);
+  };
+  NoLoad ld;
+  lds_fft<NP, F, kChanThreads, true, LdsLayout<NP, 1>>(buf, tw, tid, ld, st);
+}
+
+template <int P>
+__global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __restrict__ xt, int Np,
+                                                             const float2* __restrict__ tabs,
+                                                             float2* __restrict__ out, int64_t xtbs,
+                                                             int64_t obs) {
+  __shared__ float2 buf[kLT * P];
+  __shared__ float2 tw[1024];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * kLT;
+  const int k = blockIdx.y;
+  xt += blockIdx.z * xtbs;
+  out += blockIdx.z * obs;
+  for (int i = tid; i < 1024; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i];
+  __syncthreads();
+  const float2* rk = xt + static_cast<int64_t>(k) * P;
+  const float2* rl = xt + static_cast<int64_t>(l0) * P;
+  float2* dst = out + (static_cast<int64_t>(k) * Np + l0) * P;
+  auto ld = [&](int b, int m) { return cmulc(rk[m], rl[b * P + m]); };
+  auto st = [&](int b, int m, float2 v) { dst[b * P + m] = v; };
+  lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>>(buf, tw, tid, ld, st);
+}
+
+template <int NP>
+hipError_t chan(const float2* x, int L, int P, const float* win, const float2* tabs, float2* xt, int batch,
+                int64_t xbs, hipStream_t s) {
+  constexpr int F = 4096 / NP;
+  dim3 grid((P + F - 1) / F, batch);
+  hipLaunchKernelGGL(fam_chan_fp32<NP>, grid, dim3(kChanThreads), 0, s, x, L, P, win, tabs, xt, xbs,
+                     static_cast<int64_t>(NP) * P);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t pair(const float2* xt, int Np, const float2* tabs, float2* out, int batch, int64_t obs, hipStream_t s) {
+  dim3 grid(Np / kLT, Np, batch);
+  hipLaunchKernelGGL(fam_pair_fp32<P>, grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
+                     static_cast<int64_t>(Np) * P, obs);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs, float2* xt,
+                           float2* out, int batch, int64_t xbs, int64_t obs, hipStream_t s) {
+  hipError_t e;
+  switch (Np) {
+    case 16: e = chan<16>(x, L, P, win, tabs, xt, batch, xbs, s); break;
+    case 32: e = chan<32>(x, L, P, win, tabs, xt, batch, xbs, s); break;
+    case 64: e = chan<64>(x, L, P, win, tabs, xt, batch, xbs, s); break;
+    case 128: e = chan<128>(x, L, P, win, tabs, xt, batch, xbs, s); break;
+    case 256: e = chan<256>(x, L, P, win, tabs, xt, batch, xbs, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (P) {
+    case 4: return pair<4>(xt, Np, tabs, out, batch, obs, s);
+    case 8: return pair<8>(xt, Np, tabs, out, batch, obs, s);
+    case 16: return pair<16>(xt, Np, tabs, out, batch, obs, s);
+    case 32: return pair<32>(xt, Np, tabs, out, batch, obs, s);
+    case 64: return pair<64>(xt, Np, tabs, out, batch, obs, s);
+    case 128: return pair<128>(xt, Np, tabs, out, batch, obs, s);
+    case 256: return pair<256>(xt, Np, tabs, out, batch, obs, s);
+    case 512: return pair<512>(xt, Np, tabs, out, batch, obs, s);
+    case 1024: return pair<1024>(xt, Np, tabs, out, batch, obs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace scd

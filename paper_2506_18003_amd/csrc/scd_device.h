@@ -1,0 +1,229 @@
+// Device-side building blocks shared by the SCD kernels (gfx950, wave64).
+//
+// * complex float2 arithmetic;
+// * forward DFTs of 2, 4, 8 and 16 points held in registers (natural order in and out), with the trivial
+//   twiddles of the 8- and 16-point forms written as rotations rather than multiplications;
+// * a Stockham-ordered, mixed-radix (16, then 8/4/2) in-LDS FFT over a batch of sequences, whose first stage
+//   may read from a caller functor (e.g. straight from HBM) and whose last stage may hand its outputs to a
+//   caller functor (e.g. to apply a rotation factor and store to HBM).
+//
+// Twiddles come from an LDS copy of omega_1024^e = exp(-2 pi i e / 1024), e < 1024, which the host generates
+// in FP64 on the GPU (tables.hip); every stage of every transform here is at most 1024 points long.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace scd {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {  // acc + a*b
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+constexpr float kC8 = 0.70710678118654752440f;   // cos(pi/4)
+constexpr float kC16 = 0.92387953251128675613f;  // cos(pi/8)
+constexpr float kS16 = 0.38268343236508977173f;  // sin(pi/8)
+
+// a * omega_16^E for a compile-time exponent E (omega_16 = exp(-2 pi i / 16)).
+template <int E>
+__device__ __forceinline__ float2 rot16(float2 a) {
+  constexpr int e = ((E % 16) + 16) % 16;
+  if constexpr (e == 0) return a;
+  else if constexpr (e == 4) return mul_mi(a);
+  else if constexpr (e == 8) return make_float2(-a.x, -a.y);
+  else if constexpr (e == 12) return make_float2(-a.y, a.x);
+  else if constexpr (e == 2) return make_float2((a.x + a.y) * kC8, (a.y - a.x) * kC8);
+  else if constexpr (e == 6) return make_float2((a.y - a.x) * kC8, -(a.x + a.y) * kC8);
+  else if constexpr (e == 10) return make_float2(-(a.x + a.y) * kC8, (a.x - a.y) * kC8);
+  else if constexpr (e == 14) return make_float2((a.x - a.y) * kC8, (a.x + a.y) * kC8);
+  else {
+    // general: cos(2 pi e/16) - i sin(2 pi e/16), built from cos/sin(pi/8) by quadrant
+    constexpr int q = e / 4, r = e % 4;  // r is 1 or 3
+    constexpr float c0 = (r == 1) ? kC16 : kS16;
+    constexpr float s0 = (r == 1) ? kS16 : kC16;
+    // omega_16^r = (c0, -s0); then rotate by (-i)^q
+    float2 b = make_float2(fmaf(a.x, c0, a.y * s0), fmaf(a.y, c0, -a.x * s0));
+    if constexpr (q == 0) return b;
+    else if constexpr (q == 1) return mul_mi(b);
+    else if constexpr (q == 2) return make_float2(-b.x, -b.y);
+    else return make_float2(-b.y, b.x);
+  }
+}
+
+__device__ __forceinline__ void dft2(float2* a) {
+  float2 t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+
+__device__ __forceinline__ void dft4(float2* a) {
+  float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+  float2 s13 = cadd(a[1], a[3]), d13 = mul_mi(csub(a[1], a[3]));
+  a[0] = cadd(s02, s13);
+  a[2] = csub(s02, s13);
+  a[1] = cadd(d02, d13);
+  a[3] = csub(d02, d13);
+}
+
+// 4-point DFT of a[o], a[o+s], a[o+2s], a[o+3s], in place.
+template <int O, int S>
+__device__ __forceinline__ void dft4s(float2* a) {
+  float2 t[4] = {a[O], a[O + S], a[O + 2 * S], a[O + 3 * S]};
+  dft4(t);
+  a[O] = t[0]; a[O + S] = t[1]; a[O + 2 * S] = t[2]; a[O + 3 * S] = t[3];
+}
+
+// 8-point DFT = 2 x 4: A[n1][k2] = DFT4_{n2} a[n1 + 2 n2]; A *= w8^{n1 k2}; X[k2 + 4 k1] = DFT2_{n1}.
+__device__ __forceinline__ void dft8(float2* a) {
+  float2 e[4] = {a[0], a[2], a[4], a[6]};
+  float2 o[4] = {a[1], a[3], a[5], a[7]};
+  dft4(e);
+  dft4(o);
+  o[1] = rot16<2>(o[1]);
+  o[2] = rot16<4>(o[2]);
+  o[3] = rot16<6>(o[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = cadd(e[k], o[k]);
+    a[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+// 16-point DFT = 4 x 4: A[n1][k2] = DFT4_{n2} a[n1 + 4 n2]; A *= w16^{n1 k2}; X[k2 + 4 k1] = DFT4_{n1} A.
+__device__ __forceinline__ void dft16(float2* a) {
+  float2 t[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    float2 v[4] = {a[n1], a[n1 + 4], a[n1 + 8], a[n1 + 12]};
+    dft4(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[n1 * 4 + k2] = v[k2];
+  }
+  t[5] = rot16<1>(t[5]);  t[6] = rot16<2>(t[6]);  t[7] = rot16<3>(t[7]);
+  t[9] = rot16<2>(t[9]);  t[10] = rot16<4>(t[10]); t[11] = rot16<6>(t[11]);
+  t[13] = rot16<3>(t[13]); t[14] = rot16<6>(t[14]); t[15] = rot16<9>(t[15]);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    float2 v[4] = {t[k2], t[4 + k2], t[8 + k2], t[12 + k2]};
+    dft4(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[k2 + 4 * k1] = v[k1];
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2(a);
+  else if constexpr (R == 4) dft4(a);
+  else if constexpr (R == 8) dft8(a);
+  else if constexpr (R == 16) dft16(a);
+  else static_assert(R == 1, "unsupported radix");
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Radix of the stage that starts with sub-transform length NS in a length-L transform: 16 while at least
+// 4 bits remain, then the remaining 2^b.
+template <int L, int NS>
+struct StageRadix {
+  static constexpr int rem = ilog2(L) - ilog2(NS);
+  static constexpr int value = rem >= 4 ? 16 : (1 << rem);
+};
+
+// Default LDS addressing: element m of sequence b sits at b*BS + m*MS (+ PAD extra float2 per 16 elements
+// along m, which breaks the 16-element stride of radix-16 writes across LDS banks).
+template <int BS, int MS, int PADSH = 0>
+struct LdsLayout {
+  __device__ __forceinline__ static int at(int b, int m) {
+    if constexpr (PADSH > 0) return b * BS + (m + (m >> PADSH)) * MS;
+    else return b * BS + m * MS;
+  }
+};
+
+struct NoLoad {};
+struct NoStore {};
+
+// One Stockham stage (radix R, sub-transform length NS) over NB sequences of length L, run by NT threads.
+// Butterfly j of sequence b reads elements j + i*L/R (i < R), multiplies element i by
+// omega_{NS R}^{i (j mod NS)}, takes an R-point DFT and writes output i to (j/NS)*NS*R + (j mod NS) + i*NS.
+// BFAST selects the enumeration of butterflies over threads: sequence index fastest (true) or j fastest.
+// All threads read their inputs before the barrier and write after it, so the stage runs in place.
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, class LoadF, class StoreF>
+__device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
+  constexpr int R = StageRadix<L, NS>::value;
+  constexpr int NBF = NB * (L / R);
+  constexpr int PER = (NBF + NT - 1) / NT;
+  constexpr bool FIRST = (NS == 1);
+  constexpr bool LAST = (NS * R == L);
+  constexpr bool LOAD_EXT = FIRST && !std::is_same<LoadF, NoLoad>::value;
+  constexpr bool STORE_EXT = LAST && !std::is_same<StoreF, NoStore>::value;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int bf = tid + p * NT;
+    if (NBF % NT == 0 || bf < NBF) {
+      const int b = BFAST ? (bf % NB) : (bf / (L / R));
+      const int j = BFAST ? (bf / NB) : (bf % (L / R));
+      const int k = j % NS;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int m = j + i * (L / R);
+        if constexpr (LOAD_EXT) v[p][i] = ld(b, m);
+        else v[p][i] = buf[Lay::at(b, m)];
+      }
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int i = 1; i < R; ++i) v[p][i] = cmul(v[p][i], tw[(i * k * (1024 / (NS * R))) & 1023]);
+      }
+      dft<R>(v[p]);
+    }
+  }
+  if constexpr (!LOAD_EXT) __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int bf = tid + p * NT;
+    if (NBF % NT == 0 || bf < NBF) {
+      const int b = BFAST ? (bf % NB) : (bf / (L / R));
+      const int j = BFAST ? (bf / NB) : (bf % (L / R));
+      const int k = j % NS;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int m = (j / NS) * NS * R + k + i * NS;
+        if constexpr (STORE_EXT) st(b, m, v[p][i]);
+        else buf[Lay::at(b, m)] = v[p][i];
+      }
+    }
+  }
+  if constexpr (!STORE_EXT) __syncthreads();
+}
+
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, class LoadF, class StoreF>
+__device__ __forceinline__ void stockham_from(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
+  if constexpr (NS < L) {
+    stockham_stage<L, NB, NT, NS, BFAST, Lay>(buf, tw, tid, ld, st);
+    constexpr int R = StageRadix<L, NS>::value;
+    stockham_from<L, NB, NT, NS * R, BFAST, Lay>(buf, tw, tid, ld, st);
+  }
+}
+
+// Forward DFT of NB length-L sequences (L a power of two, 2 <= L <= 1024), natural order in and out.
+// Requires a barrier before the call if the data were just written to LDS by other threads. On return the
+// outputs are either in LDS (followed by a barrier) or were handed to `st(b, m, value)`.
+template <int L, int NB, int NT, bool BFAST, class Lay, class LoadF, class StoreF>
+__device__ __forceinline__ void lds_fft(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
+  static_assert(L >= 2 && L <= 1024 && (L & (L - 1)) == 0, "length must be a power of two in [2, 1024]");
+  stockham_from<L, NB, NT, 1, BFAST, Lay>(buf, tw, tid, ld, st);
+}
+
+}  // namespace scd

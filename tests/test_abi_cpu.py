@@ -1,0 +1,109 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function include/scd.h declares, and
+rejects bad arguments with the documented codes before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2506_18003_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(scd_[a-z_0-9]+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libscd.so not built")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "scd_ssca" in names and "scd_fam" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version(L):
+    assert L.scd_version() >> 16 == 1
+
+
+def _fake(addr):
+    return ctypes.c_void_p(addr)
+
+
+X, W, O = 0x10000000, 0x20000000, 0x30000000
+
+
+@pytest.mark.parametrize("N,Np,code", [
+    (1000, 32, _lib.SCD_ERR_SIZE), (512, 32, _lib.SCD_ERR_SIZE), (1 << 21, 32, _lib.SCD_ERR_SIZE),
+    (1024, 8, _lib.SCD_ERR_SIZE), (1024, 512, _lib.SCD_ERR_SIZE), (1024, 48, _lib.SCD_ERR_SIZE),
+])
+def test_ssca_size_errors(L, N, Np, code):
+    assert L.scd_ssca(_fake(X), N, Np, _fake(W), _fake(O)) == code
+    assert L.scd_last_error()
+
+
+def test_ssca_null_and_alias(L):
+    assert L.scd_ssca(None, 1024, 32, _fake(W), _fake(O)) == _lib.SCD_ERR_NULL
+    assert L.scd_ssca(_fake(X), 1024, 32, None, _fake(O)) == _lib.SCD_ERR_NULL
+    assert L.scd_ssca(_fake(X), 1024, 32, _fake(W), None) == _lib.SCD_ERR_NULL
+    # out overlapping x
+    assert L.scd_ssca(_fake(X), 1024, 32, _fake(W), _fake(X + 64)) == _lib.SCD_ERR_ALIAS
+    # out overlapping win
+    assert L.scd_ssca(_fake(X), 1024, 32, _fake(O + 8 * 1024), _fake(O)) == _lib.SCD_ERR_ALIAS
+
+
+def test_ssca_ex_option_errors(L):
+    o = _lib.ScdOpts()
+    o.precision = 9
+    assert L.scd_ssca_ex(_fake(X), 1024, 32, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_SIZE
+    o = _lib.ScdOpts()
+    o.batch = 2
+    o.x_stride = 100  # < N
+    assert L.scd_ssca_ex(_fake(X), 1024, 32, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_SIZE
+    o = _lib.ScdOpts()
+    o.workspace_bytes = 10
+    assert L.scd_ssca_ex(_fake(X), 1024, 32, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_NULL
+    o = _lib.ScdOpts()
+    o.workspace = X + 8
+    o.workspace_bytes = 1 << 20
+    assert L.scd_ssca_ex(_fake(X), 2048, 32, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_ALIAS
+    o = _lib.ScdOpts()
+    o.workspace = 0x50000000
+    o.workspace_bytes = 1024
+    assert L.scd_ssca_ex(_fake(X), 2048, 32, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_NOMEM
+
+
+@pytest.mark.parametrize("Np,Lh,P,code", [
+    (32, 8, 3, _lib.SCD_ERR_SIZE), (32, 64, 32, _lib.SCD_ERR_SIZE), (32, 3, 32, _lib.SCD_ERR_SIZE),
+    (8, 2, 32, _lib.SCD_ERR_SIZE), (32, 8, 2048, _lib.SCD_ERR_SIZE), (256, 256, 512, _lib.SCD_ERR_SIZE),
+])
+def test_fam_size_errors(L, Np, Lh, P, code):
+    assert L.scd_fam(_fake(X), Np, Lh, P, _fake(W), _fake(O)) == code
+
+
+def test_fam_alias_and_null(L):
+    assert L.scd_fam(None, 32, 8, 32, _fake(W), _fake(O)) == _lib.SCD_ERR_NULL
+    assert L.scd_fam(_fake(X), 32, 8, 32, _fake(W), _fake(X)) == _lib.SCD_ERR_ALIAS
+
+
+def test_workspace_size(L):
+    v = ctypes.c_size_t()
+    assert L.scd_ssca_workspace_size(1 << 20, 64, 1, ctypes.byref(v)) == 0
+    assert v.value == 8 * 64 * (1 << 20)
+    assert L.scd_ssca_workspace_size(1024, 64, 3, ctypes.byref(v)) == 0 and v.value == 0
+    assert L.scd_ssca_workspace_size(1000, 64, 1, ctypes.byref(v)) == _lib.SCD_ERR_SIZE
+    assert L.scd_fam_workspace_size(256, 64, 256, 16, ctypes.byref(v)) == 0
+    assert v.value == 8 * 256 * 256 * 16
+    assert L.scd_ssca_workspace_size(1024, 64, 1, None) == _lib.SCD_ERR_NULL
