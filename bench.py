@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forms", default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the SSCA strips would shard over GPUs by channel, but this "
@@ -81,6 +83,15 @@ def main():
     inter = torch.empty(Np * N, dtype=torch.complex64, device=dev)
     out = torch.empty(Np, N, dtype=torch.complex64, device=dev)
     stream = torch.cuda.current_stream(dev)
+
+    if args.copy_calib:
+        src = torch.empty(32 << 20, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        src.zero_()
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}

@@ -97,7 +97,8 @@ typedef struct scd_opts {
  *   out  device, Np*N complex values, row-major [Np][N]
  * Errors: SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_ALIAS, SCD_ERR_PTR, SCD_ERR_NOMEM, SCD_ERR_HIP.
  * Uses a library-owned intermediate of 8*Np*N bytes when N > 1024. That buffer is shared by every call
- * on the device that passes no workspace: such calls must not run concurrently on different streams.
+ * on the device that passes no workspace, and a small per-(N, Np) scratch holding the window's channel-subset
+ * forms is shared by every call: calls on one device must not run concurrently on different streams.
  */
 int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out);
 

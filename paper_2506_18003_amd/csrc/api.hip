@@ -22,7 +22,7 @@ std::mutex g_mu;
 hipStream_t g_stream = nullptr;
 
 struct DevState {
-  std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables
+  std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables + window scratch
   void* work = nullptr;
   size_t work_bytes = 0;
 };
@@ -83,7 +83,7 @@ int check_device_range(const void* p, size_t bytes, const char* name) {
 
 // Tables for (transform length n, Np): omega_1024, omega_n^j (j < 1024) and omega_Np. Generated once in FP64
 // on the GPU; creation waits for the generation to finish so any stream may use them afterwards.
-int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, const float2** out) {
+int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, float2** out) {
   auto key = std::make_pair(n, Np);
   auto it = st.plans.find(key);
   if (it != st.plans.end()) {
@@ -91,7 +91,7 @@ int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, const float2** ou
     return SCD_OK;
   }
   float2* t = nullptr;
-  hipError_t e = hipMalloc(&t, sizeof(float2) * scd::kTabSize);
+  hipError_t e = hipMalloc(&t, sizeof(float2) * (scd::kTabSize + scd::kHcFloats));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SCD_ERR_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
@@ -252,14 +252,15 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   int dev;
   if ((rc = current_device(&dev))) return rc;
   DevState& st = g_dev[dev];
-  const float2* tabs;
+  float2* tabs;
   if ((rc = get_tables(st, N, Np, r.stream, &tabs))) return rc;
+  float2* hc = tabs + scd::kTabSize;
   const float2* ic = reinterpret_cast<const float2*>(in);
   float2* oc = reinterpret_cast<float2*>(dst);
   const int n = static_cast<int>(N);
   hipError_t e = hipSuccess;
   if (part == SscaPart::kStage1) {
-    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, oc, r.batch, r.xs, r.os, r.stream);
+    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, hc, oc, r.batch, r.xs, r.os, r.stream);
   } else if (part == SscaPart::kStage2) {
     if (N == 1024) {
       // The Stage 1 output already is the result; copy it if the caller asked for another buffer.
@@ -271,7 +272,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     }
   } else if (per == 0) {
     // N == 1024: the Stage 1 output is the final result.
-    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, oc, r.batch, r.xs, r.os, r.stream);
+    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, hc, oc, r.batch, r.xs, r.os, r.stream);
   } else {
     int chunk = r.batch;
     void* work = r.work;
@@ -283,7 +284,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     float2* T = static_cast<float2*>(work);
     for (int b0 = 0; b0 < r.batch && e == hipSuccess; b0 += chunk) {
       const int nb = std::min(chunk, r.batch - b0);
-      e = scd::launch_ssca_pass1_fp32(ic + b0 * r.xs, n, Np, win, tabs, T, nb, r.xs, grid, r.stream);
+      e = scd::launch_ssca_pass1_fp32(ic + b0 * r.xs, n, Np, win, tabs, hc, T, nb, r.xs, grid, r.stream);
       if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc + b0 * r.os, nb, grid, r.os, r.stream);
     }
   }
@@ -342,7 +343,7 @@ int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* ou
   int dev;
   if ((rc = current_device(&dev))) return rc;
   DevState& st = g_dev[dev];
-  const float2* tabs;
+  float2* tabs;
   if ((rc = get_tables(st, 1024, Np, r.stream, &tabs))) return rc;
   int chunk = r.batch;
   void* work = r.work;

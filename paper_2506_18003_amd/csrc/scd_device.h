@@ -31,6 +31,37 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 // multiply by -i
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
+// Raw buffer resource over `bytes` bytes at p (gfx9 word 3). Loads through it at byte offsets >= bytes (which
+// includes negative element indices converted to unsigned) return zero, so out-of-range samples read as the
+// zero padding of the signal without a compare or a fault.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
+}
+
+// The complex sample at element index idx (may be negative or past the end: zero then).
+__device__ __forceinline__ float2 load_c64(__amdgpu_buffer_rsrc_t r, int idx) {
+  // Bit-cast the whole 64-bit result: extracting its two lanes separately let the compiler drop the second
+  // dword of the load.
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<unsigned>(idx) * 8u, 0, 0));
+}
+
+// Streaming (nontemporal) 16-byte global accesses of two adjacent complex values.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ld2_nt(const float2* p, float2& a, float2& b) {
+  const v4f_t t = __builtin_nontemporal_load(reinterpret_cast<const v4f_t*>(p));
+  a = make_float2(t.x, t.y);
+  b = make_float2(t.z, t.w);
+}
+__device__ __forceinline__ void st2_nt(float2* p, float2 a, float2 b) {
+  const v4f_t t = {a.x, a.y, b.x, b.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<v4f_t*>(p));
+}
+__device__ __forceinline__ void st1_nt(float2* p, float2 a) {
+  typedef float v2f_t __attribute__((ext_vector_type(2)));
+  const v2f_t t = {a.x, a.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<v2f_t*>(p));
+}
+
 constexpr float kC8 = 0.70710678118654752440f;   // cos(pi/4)
 constexpr float kC16 = 0.92387953251128675613f;  // cos(pi/8)
 constexpr float kS16 = 0.38268343236508977173f;  // sin(pi/8)
@@ -215,6 +246,55 @@ __device__ __forceinline__ void stockham_from(float2* buf, const float2* tw, int
     constexpr int R = StageRadix<L, NS>::value;
     stockham_from<L, NB, NT, NS * R, BFAST, Lay>(buf, tw, tid, ld, st);
   }
+}
+
+// First stage of a length-L transform split in two, so a caller can start the first stage's loads early:
+// FirstStage<...>::gather reads its inputs through `ld` into registers; FirstStage<...>::scatter takes the
+// R-point DFTs and writes the results to LDS, followed by a barrier. Then stockham_rest runs the remaining
+// stages.
+template <int L, int NB, int NT, bool BFAST>
+struct FirstStage {
+  static constexpr int R = StageRadix<L, 1>::value;
+  static constexpr int NBF = NB * (L / R);
+  static constexpr int PER = (NBF + NT - 1) / NT;
+  template <class LoadF>
+  __device__ __forceinline__ static void gather(float2 (&v)[PER][R], int tid, LoadF& ld) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int bf = tid + p * NT;
+      if (NBF % NT == 0 || bf < NBF) {
+        const int b = BFAST ? (bf % NB) : (bf / (L / R));
+        const int j = BFAST ? (bf / NB) : (bf % (L / R));
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[p][i] = ld(b, j + i * (L / R));
+      }
+    }
+  }
+  // When this stage is the only one (R == L) its outputs go to `st`; otherwise to LDS, then a barrier.
+  template <class Lay, class StoreF>
+  __device__ __forceinline__ static void scatter(float2 (&v)[PER][R], float2* buf, int tid, StoreF& st) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int bf = tid + p * NT;
+      if (NBF % NT == 0 || bf < NBF) {
+        const int b = BFAST ? (bf % NB) : (bf / (L / R));
+        const int j = BFAST ? (bf / NB) : (bf % (L / R));
+        dft<R>(v[p]);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if constexpr (R == L) st(b, i, v[p][i]);
+          else buf[Lay::at(b, j * R + i)] = v[p][i];
+        }
+      }
+    }
+    if constexpr (R != L) __syncthreads();
+  }
+};
+
+template <int L, int NB, int NT, bool BFAST, class Lay, class StoreF>
+__device__ __forceinline__ void stockham_rest(float2* buf, const float2* tw, int tid, StoreF& st) {
+  NoLoad ld;
+  stockham_from<L, NB, NT, StageRadix<L, 1>::value, BFAST, Lay>(buf, tw, tid, ld, st);
 }
 
 // Forward DFT of NB length-L sequences (L a power of two, 2 <= L <= 1024), natural order in and out.

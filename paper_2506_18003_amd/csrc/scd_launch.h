@@ -10,14 +10,16 @@ constexpr int kTabTw1024 = 0;     // omega_1024^j, j < 1024
 constexpr int kTabRotLo = 1024;   // omega_N^j,    j < 1024 (SSCA rotation factors, low part)
 constexpr int kTabRoots = 2048;   // omega_Np^e,   e < Np   (down-conversion factors)
 constexpr int kTabSize = 2048 + 256;
+constexpr int kHcFloats = 16 * 256;  // complex windows of every channel subset (S * Np <= 4096)
 
 hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 
 // SSCA Stage 1 (channelizer + CDP + M1-point DFT + rotation) of `batch` signals. x: [batch][N] at stride xbs;
 // T: [batch] blocked intermediates [Np][M1/16][M2][16] at stride tbs (float2 elements). With N == 1024 the
-// intermediate layout equals the output layout [Np][N].
-hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* T,
-                                  int batch, int64_t xbs, int64_t tbs, hipStream_t stream);
+// intermediate layout equals the output layout [Np][N]. hc: kHcFloats float2 of device scratch that this call
+// fills with the subsets' complex windows before stage 1 reads them.
+hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
+                                  float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t stream);
 
 // SSCA Stage 2 (M2-point DFT over m2) of `batch` intermediates into out: [batch][Np][N] at stride obs. A no-op
 // when N == 1024.

@@ -4,12 +4,12 @@
 // Pass 1 (one workgroup per (m2, channel subset)): generates the channel-data product X_g only where Stage 1
 // needs it. For every m1 it forms the centred, windowed frame n = m1*M2 + m2 (Eq. (3), L = 1), evaluates the
 // 16 channels k = c + S*k' (S = Np/16) of the subset with a pruned DFT, applies the down-conversion factor
-// omega_Np^{(k n) mod Np} and the conjugate sample conj(x[n]) (Eq. (6)), and writes X_g(m1, m2, k) into an
-// LDS column. It then takes the M1-point DFT of each column (Stage 1), multiplies by the rotation factor
+// omega_Np^{(k n) mod Np} and the conjugate sample conj(x[n]) (Eq. (6)), and keeps X_g(m1, m2, k) in
+// registers. It then takes the M1-point DFT over m1 (Stage 1), multiplies by the rotation factor
 // omega_N^{m2 m1'} and stores the result to HBM in a blocked layout T[k][m1'/16][m2][m1' % 16], so both this
 // store and pass 2's load move whole 128-byte runs.
 //
-// Pass 2 (one workgroup per (16 consecutive m1', k)): Stage 2, the M2-point DFT over m2 of 16 rows at once,
+// Pass 2 (one workgroup per (16 consecutive m1', k)): Stage 2, the M2-point DFT over m2 of the 16 rows,
 // stored at S[k][q] with q = m1' + M1*m2' (16 consecutive q per run).
 //
 // Pruned channel-subset DFT: with j = j0 + 16*j1 (j0 < 16, j1 < S) and k = c + S*k',
@@ -25,80 +25,219 @@ namespace scd {
 namespace {
 
 constexpr int kM1 = 1024;
-constexpr int kP1Threads = 256;
-constexpr int kCols = 16;
-constexpr int kColStride = kM1 + kM1 / 16;  // one float2 of padding per 16 elements
+constexpr int kP1Threads = 256;       // one frame per thread in each chunk of 256 frames
+constexpr int kSeq = 256;             // the M1-point DFT is 4 (registers) x 256 (LDS)
+constexpr int kSeqStride = kSeq + kSeq / 16;  // one float2 of padding per 16 elements
+constexpr int kHalfSeqs = 32;         // 8 channels x 4 residues per LDS exchange
+constexpr int kXchgFloats = kHalfSeqs * kSeqStride;
 constexpr int kP2Threads = 256;
 
-template <int NP>
-__global__ __launch_bounds__(kP1Threads) void ssca_pass1_fp32(const float2* __restrict__ x, int N, int M2,
-                                                             int m2shift, const float* __restrict__ win,
-                                                             const float2* __restrict__ tabs,
-                                                             float2* __restrict__ T, int64_t xbs, int64_t tbs) {
+// Complex window of channel subset c: hc[c][j] = w[j] * omega_Np^{(c j) mod Np}.
+__global__ void ssca_hc_kernel(const float* __restrict__ win, const float2* __restrict__ tabs,
+                               float2* __restrict__ hc, int Np, int S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < S * Np) {
+    const int c = e / Np, j = e % Np;
+    hc[e] = cscale(tabs[kTabRoots + ((c * j) & (Np - 1))], win[j]);
+  }
+}
+
+// omega_N^a for 0 <= a < N from the two-level table: omega_N^{a mod 1024} * omega_1024^{(a / 1024) * 1024 / M2}.
+__device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
+  return cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
+}
+
+// Stage 1. The flattened block index is mapped so that each of the 8 XCDs (which receive blocks round-robin)
+// walks a contiguous range of m2: the frames of neighbouring m2 overlap in all but one sample, so an XCD's
+// share of x stays in its L2. Thread t owns frames m1 = t + 256 f (f < 4). Frame samples are staged through
+// two LDS buffers (JS samples of 256 frames each), the next sub-chunk's loads in flight while the current one
+// is folded. Each thread folds its frame with the subset's complex window (read through the scalar cache),
+// takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does not divide M2, by the per-frame
+// down-conversion factor), keeping the 16 channel values in registers. The M1 = 1024-point DFT over
+// m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle omega_1024^{t r}, and a 256-point DFT over t
+// in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its last radix stage stores to HBM, multiplying by
+// the rotation factor omega_N^{m2 m1'} (and by the down-conversion factor omega_Np^{(k m2) mod Np}, which
+// does not depend on m1 when Np divides M2), built per butterfly as a base times a per-block step table.
+template <int NP, bool PHASE_BY_M2>
+__global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* __restrict__ x, int N, int M2,
+                                                                int m2shift, const float2* __restrict__ hcg,
+                                                                const float2* __restrict__ tabs,
+                                                                float2* __restrict__ T, int64_t xbs, int64_t tbs) {
   constexpr int S = NP / 16;
   constexpr int D = NP / 2 - 1;
-  __shared__ float2 col[kCols * kColStride];
+  constexpr int JS = NP < 16 ? NP : 16;  // samples per sub-chunk
+  constexpr int NSUB = NP / JS;
+  constexpr int kStage = kP1Threads * (JS + 1);
+  static_assert(2 * kStage >= kXchgFloats, "exchange must fit in the staging buffers");
+  __shared__ float2 buf[2 * kStage];
   __shared__ float2 tw[1024];
-  __shared__ float2 rlo[1024];
-  __shared__ float2 hc[NP];
+  __shared__ float2 stp[16];
   __shared__ float2 rt[NP];
 
   const int tid = threadIdx.x;
-  const int m2 = blockIdx.x;
-  const int c = blockIdx.y;
-  x += blockIdx.z * xbs;
-  T += blockIdx.z * tbs;
+  const int nblk = gridDim.x;
+  int lin = blockIdx.x;
+  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
+  const int c = lin >> m2shift;
+  const int m2 = lin & (M2 - 1);
+  x += blockIdx.y * xbs;
+  T += blockIdx.y * tbs;
+  const float2* rlo = tabs + kTabRotLo;
+  const float2* hc = hcg + c * NP;
+  const auto xr = make_rsrc(x, N * 8);
+  const int hishift = 10 - m2shift;
 
-  for (int i = tid; i < 1024; i += kP1Threads) {
-    tw[i] = tabs[kTabTw1024 + i];
-    rlo[i] = tabs[kTabRotLo + i];
+  for (int i = tid; i < 1024; i += kP1Threads) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < NP; i += kP1Threads) rt[i] = tabs[kTabRoots + i];
+  if (tid < 16) {
+    const float2* tw_g = tabs + kTabTw1024;
+    stp[tid] = rot_factor(rlo, tw_g, 64 * m2 * tid, hishift);
   }
-  for (int i = tid; i < NP; i += kP1Threads) {
-    const float2 r = tabs[kTabRoots + i];
-    rt[i] = r;
-    hc[i] = cscale(tabs[kTabRoots + ((c * i) & (NP - 1))], win[i]);
-  }
-  __syncthreads();
 
-  // Channelizer, down-conversion and channel-data product for frames m1 = tid + f*256.
-#pragma unroll 1
-  for (int f = 0; f < kM1 / kP1Threads; ++f) {
-    const int m1 = tid + f * kP1Threads;
-    const int n = m1 * M2 + m2;
-    const int base = n - D;
+  // Sub-chunk s covers frames m1 = 256 (s / NSUB) + i, i < 256, samples JS * (s % NSUB) + jj, jj < JS.
+  float2 pf[JS];
+  auto issue = [&](int s) {
+    const int jbase = (256 * (s / NSUB)) * M2 + m2 - D + (s % NSUB) * JS;
+#pragma unroll
+    for (int q = 0; q < JS; ++q) {
+      const int e = tid + kP1Threads * q;
+      pf[q] = load_c64(xr, jbase + (e / JS) * M2 + (e % JS));
+    }
+  };
+  auto stash = [&](int s) {
+    float2* b = buf + (s & 1) * kStage;
+#pragma unroll
+    for (int q = 0; q < JS; ++q) {
+      const int e = tid + kP1Threads * q;
+      b[(e / JS) * (JS + 1) + (e % JS)] = pf[q];
+    }
+  };
+  issue(0);
+  stash(0);
+  if (NSUB * 4 > 1) issue(1);
+
+  float2 col[4][16];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
     float2 u[16];
 #pragma unroll
     for (int j0 = 0; j0 < 16; ++j0) u[j0] = make_float2(0.f, 0.f);
+#pragma unroll 1
+    for (int sub = 0; sub < NSUB; ++sub) {
+      const int s = f * NSUB + sub;
+      __syncthreads();
+      const float2* b = buf + (s & 1) * kStage + tid * (JS + 1);
 #pragma unroll
-    for (int j1 = 0; j1 < S; ++j1) {
-#pragma unroll
-      for (int j0 = 0; j0 < 16; ++j0) {
-        const int idx = base + j0 + 16 * j1;
-        const float2 xv = (static_cast<unsigned>(idx) < static_cast<unsigned>(N)) ? x[idx] : make_float2(0.f, 0.f);
-        u[j0] = cfma(u[j0], hc[j0 + 16 * j1], xv);
-      }
+      for (int jj = 0; jj < JS; ++jj) u[jj & 15] = cfma(u[jj & 15], hc[sub * JS + jj], b[jj]);
+      if (s + 1 < 4 * NSUB) stash(s + 1);
+      if (s + 2 < 4 * NSUB) issue(s + 2);
     }
     dft16(u);
-    const float2 xn = x[n];
+    const int n = (tid + 256 * f) * M2 + m2;
+    const float2 xn = load_c64(xr, n);
 #pragma unroll
     for (int kp = 0; kp < 16; ++kp) {
-      const int k = c + S * kp;
-      const float2 pc = cmulc(rt[(k * n) & (NP - 1)], xn);
-      col[kp * kColStride + m1 + (m1 >> 4)] = cmul(u[kp], pc);
+      if constexpr (PHASE_BY_M2) {
+        col[f][kp] = cmulc(u[kp], xn);
+      } else {
+        const int k = c + S * kp;
+        col[f][kp] = cmul(u[kp], cmulc(rt[(k * n) & (NP - 1)], xn));
+      }
     }
   }
-  __syncthreads();
 
-  // Stage 1: M1-point DFT over m1, rotation omega_N^{m2 m1'}, blocked store.
-  const int hishift = 10 - m2shift;  // omega_N^{1024 a_hi} = omega_1024^{a_hi * 1024 / M2}
-  auto st = [&](int b, int m, float2 v) {
-    const int k = c + S * b;
-    const int a = m2 * m;
-    const float2 rot = cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
-    T[((k * (kM1 / 16) + (m >> 4)) * M2 + m2) * 16 + (m & 15)] = cmul(v, rot);
-  };
-  NoLoad ld;
-  lds_fft<kM1, kCols, kP1Threads, false, LdsLayout<kColStride, 1, 4>>(col, tw, tid, ld, st);
+  // 4-point DFT over f and twiddle omega_1024^{t r}: col[r][k'] now holds residue r of channel k'.
+  const float2 t1 = tw[tid], t2 = tw[2 * tid], t3 = tw[3 * tid];
+#pragma unroll
+  for (int kp = 0; kp < 16; ++kp) {
+    float2 a[4] = {col[0][kp], col[1][kp], col[2][kp], col[3][kp]};
+    dft4(a);
+    col[0][kp] = a[0];
+    col[1][kp] = cmul(a[1], t1);
+    col[2][kp] = cmul(a[2], t2);
+    col[3][kp] = cmul(a[3], t3);
+  }
+
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(kk * 4 + r) * kSeqStride + tid + (tid >> 4)] = col[r][8 * h + kk];
+    }
+    __syncthreads();
+    // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i.
+    auto st = [&](int b, int m, float2 v) {
+      const int k = c + S * (8 * h + (b >> 2));
+      const int rj = (b & 3) + 4 * (m & 15);
+      float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
+      if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
+      const int i = m >> 4;
+      st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+    };
+    NoLoad ld;
+    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
+  }
+}
+
+// Stage 2. A workgroup owns 16 consecutive m1' of channel k: one 128-byte run of the blocked intermediate per
+// m2, and one 128-byte run of the output per m2'. Each thread works on pairs of adjacent rows, so every global
+// and LDS access moves 16 bytes; element (row b, m) sits at LDS m*16 + b. The stage structure is the
+// Stockham one of lds_fft, applied to row pairs: the first stage streams straight from HBM and the last
+// stage streams straight to HBM (nontemporal: each byte is touched once).
+template <int L, int NS>
+__device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2* __restrict__ dst, float2* buf,
+                                         const float2* tw, int tid) {
+  constexpr int R = StageRadix<L, NS>::value;
+  constexpr int NBF = 8 * (L / R);  // (row pair, butterfly) work items
+  constexpr int PER = (NBF + kP2Threads - 1) / kP2Threads;
+  constexpr bool FIRST = NS == 1, LAST = NS * R == L;
+  float2 a[PER][R], b[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int bf = tid + p * kP2Threads;
+    if (NBF % kP2Threads == 0 || bf < NBF) {
+      const int rp = bf & 7, j = bf >> 3, k = j % NS;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int m = j + i * (L / R);
+        if constexpr (FIRST) {
+          ld2_nt(src + m * 16 + 2 * rp, a[p][i], b[p][i]);
+        } else {
+          const float4 t = *reinterpret_cast<const float4*>(buf + m * 16 + 2 * rp);
+          a[p][i] = make_float2(t.x, t.y);
+          b[p][i] = make_float2(t.z, t.w);
+        }
+      }
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int i = 1; i < R; ++i) {
+          const float2 w = tw[(i * k * (1024 / (NS * R))) & 1023];
+          a[p][i] = cmul(a[p][i], w);
+          b[p][i] = cmul(b[p][i], w);
+        }
+      }
+      dft<R>(a[p]);
+      dft<R>(b[p]);
+    }
+  }
+  if constexpr (!FIRST) __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int bf = tid + p * kP2Threads;
+    if (NBF % kP2Threads == 0 || bf < NBF) {
+      const int rp = bf & 7, j = bf >> 3, k = j % NS;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int m = (j / NS) * NS * R + k + i * NS;
+        if constexpr (LAST) st2_nt(dst + 2 * rp + kM1 * m, a[p][i], b[p][i]);
+        else *reinterpret_cast<float4*>(buf + m * 16 + 2 * rp) = make_float4(a[p][i].x, a[p][i].y, b[p][i].x, b[p][i].y);
+      }
+    }
+  }
+  if constexpr (!LAST) __syncthreads();
+  if constexpr (!LAST) p2_stage<L, NS * R>(src, dst, buf, tw, tid);
 }
 
 template <int M2>
@@ -115,16 +254,21 @@ __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __re
   __syncthreads();
   const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (M2 * 16);
   float2* dst = out + blockIdx.z * obs + static_cast<int64_t>(k) * N + mb * 16;
-  auto ld = [&](int b, int m) { return src[m * 16 + b]; };
-  auto st = [&](int b, int m, float2 v) { dst[b + kM1 * m] = v; };
-  lds_fft<M2, 16, kP2Threads, true, LdsLayout<1, 16>>(buf, tw, tid, ld, st);
+  p2_stage<M2, 1>(src, dst, buf, tw, tid);
 }
 
 template <int NP>
-hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* T,
-                 int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
-  dim3 grid(M2, NP / 16, batch);
-  hipLaunchKernelGGL(ssca_pass1_fp32<NP>, grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, win, tabs, T, xbs, tbs);
+hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* hc,
+                 float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+  constexpr int S = NP / 16;
+  hipLaunchKernelGGL(ssca_hc_kernel, dim3((S * NP + 255) / 256), dim3(256), 0, s, win, tabs, hc, NP, S);
+  dim3 grid(M2 * S, batch);
+  if (M2 % NP == 0)
+    hipLaunchKernelGGL((ssca_pass1_fp32<NP, true>), grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T,
+                       xbs, tbs);
+  else
+    hipLaunchKernelGGL((ssca_pass1_fp32<NP, false>), grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T,
+                       xbs, tbs);
   return hipGetLastError();
 }
 
@@ -138,17 +282,17 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int Np
 
 }  // namespace
 
-hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* T,
-                                  int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
+                                  float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, s);
-    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, s);
-    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, s);
-    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, s);
-    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, s);
+    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
+    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
+    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
+    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
+    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,56 @@
+"""CPU checks of the gfx950 code the SSCA kernels compile to (no GPU needed).
+
+* Every out-of-range-safe sample load is one 64-bit buffer load with the whole offset in the range-checked
+  VGPR operand; a split or narrowed load would read past the signal instead of the zero padding.
+* The headline Stage-1 kernel (Np = 64, Np dividing M2) and the Stage-2 kernels do not spill registers.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2506_18003_amd", "csrc")
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def _hipcc():
+    return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_hipcc()), reason="hipcc not available")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    out = tmp_path_factory.mktemp("asm") / "ssca.s"
+    subprocess.run([_hipcc(), *FLAGS, "-S", "--cuda-device-only", os.path.join(CSRC, "ssca_fp32.hip"), "-o",
+                    str(out)], check=True, capture_output=True)
+    return out.read_text()
+
+
+def test_sample_loads_are_single_64bit_range_checked(asm):
+    loads = [ln.split() for ln in asm.splitlines() if "buffer_load" in ln]
+    assert loads
+    for ins in loads:
+        assert ins[0] == "buffer_load_dwordx2", ins
+        # operands: vdst, voffset, srsrc, soffset(0), offen; no immediate offset outside the range check
+        assert ins[-2:] == ["0", "offen"], ins
+
+
+def _spills(asm):
+    out = {}
+    for m in re.finditer(r"\.name:\s+(\S+)(.*?)\.vgpr_spill_count:\s+(\d+)", asm, re.S):
+        out[m.group(1)] = int(m.group(3))
+    return out
+
+
+def test_hot_kernels_do_not_spill(asm):
+    sp = _spills(asm)
+    hot = [n for n in sp if "ssca_pass1_fp32ILi64ELb1E" in n or "ssca_pass2_fp32" in n]
+    assert any("pass1" in n for n in hot) and any("pass2" in n for n in hot)
+    for n in hot:
+        assert sp[n] == 0, n
