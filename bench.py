@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 METRIC = "SCD pts/s, SSCA N=2^20 N'=64: FP32 vs split-BF16 vs learned strips"
 PAPER_PTS_PER_S = 2 ** 26 / 0.114  # VCK5000, 114 ms per SSCA estimate at N=2^20, N_P=64 (Table III)
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("scd_device.h", "ssca_fp32.hip")
+KERNEL_SOURCES = ("scd_device.h", "ssca_fp32.hip", "ssca_mfma.hip")
 
 
 def source_digest(files=KERNEL_SOURCES) -> str:
@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp32")
+    ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -169,6 +169,8 @@ def main():
                       "ms_per_step": round(rr["ms_per_step"], 5), "p10_ms": round(rr["step_ms_p10"], 5),
                       "p50_ms": round(rr["step_ms_p50"], 5), "p90_ms": round(rr["step_ms_p90"], 5),
                       "pass1_ms": round(rr["pass1_ms"], 5), "pass2_ms": round(rr["pass2_ms"], 5),
+                      "speedup_vs_fp32": (round(results["fp32"]["ms_per_step"] / rr["ms_per_step"], 3)
+                                          if "fp32" in results else None),
                       "max_err_vs_oracle": errs.get(f)} for f, rr in results.items()},
     }
     print(json.dumps(line), flush=True)

@@ -25,6 +25,8 @@ struct DevState {
   std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables + window scratch
   void* work = nullptr;
   size_t work_bytes = 0;
+  void* aux = nullptr;  // 16-bit copies of x and MFMA weights of the split-precision channelizer
+  size_t aux_bytes = 0;
 };
 std::map<int, DevState> g_dev;
 
@@ -109,31 +111,35 @@ int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, float2** out) {
   return SCD_OK;
 }
 
-// Library-owned workspace of at least `bytes`, grown on demand.
-int get_work(DevState& st, size_t bytes, void** out) {
+// Library-owned device buffer of at least `bytes`, grown on demand (the old one is freed after the device
+// drains, since queued kernels may still use it).
+int grow(void** buf, size_t* have, size_t bytes, void** out) {
   if (bytes == 0) {
     *out = nullptr;
     return SCD_OK;
   }
-  if (st.work_bytes < bytes) {
-    if (st.work) {
+  if (*have < bytes) {
+    if (*buf) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
-      (void)hipFree(st.work);
-      st.work = nullptr;
-      st.work_bytes = 0;
+      (void)hipFree(*buf);
+      *buf = nullptr;
+      *have = 0;
     }
-    hipError_t e = hipMalloc(&st.work, bytes);
+    hipError_t e = hipMalloc(buf, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      st.work = nullptr;
-      return fail(SCD_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      *buf = nullptr;
+      return fail(SCD_ERR_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
-    st.work_bytes = bytes;
+    *have = bytes;
   }
-  *out = st.work;
+  *out = *buf;
   return SCD_OK;
 }
+
+int get_work(DevState& st, size_t bytes, void** out) { return grow(&st.work, &st.work_bytes, bytes, out); }
+int get_aux(DevState& st, size_t bytes, void** out) { return grow(&st.aux, &st.aux_bytes, bytes, out); }
 
 int current_device(int* dev) {
   hipError_t e = hipGetDevice(dev);
@@ -148,6 +154,8 @@ struct Resolved {
   hipStream_t stream = nullptr;
   void* work = nullptr;
   size_t work_bytes = 0;
+  void* aux = nullptr;  // 16-bit copies of x and MFMA weights of the split-precision channelizer
+  size_t aux_bytes = 0;
 };
 
 int resolve(const scd_opts* o, int64_t xlen, int64_t olen, Resolved* r) {
@@ -229,8 +237,8 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   int rc = resolve(opts, inlen, grid, &r);
   if (rc) return rc;
   if (r.precision < SCD_FP32 || r.precision > SCD_FP16) return fail(SCD_ERR_SIZE, "unknown precision %d", r.precision);
-  if (r.precision != SCD_FP32 && part != SscaPart::kStage2)
-    return fail(SCD_ERR_UNSUPPORTED, "precision %d is not available in this build", r.precision);
+  if (r.precision != SCD_FP32 && part != SscaPart::kStage2 && Np > 128)
+    return fail(SCD_ERR_UNSUPPORTED, "16-bit channelizer precisions support Np <= 128 (got %d)", Np);
   const size_t ib = span_bytes(r.batch, r.xs, inlen);
   const size_t ob = span_bytes(r.batch, r.os, grid);
   const size_t wb = need_win ? 4u * static_cast<size_t>(Np) : 0;
@@ -258,9 +266,17 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   const float2* ic = reinterpret_cast<const float2*>(in);
   float2* oc = reinterpret_cast<float2*>(dst);
   const int n = static_cast<int>(N);
+  const int prec = r.precision;
+  // Stage 1 in the requested precision, for nb signals.
+  auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
+    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, hc, T, nb, r.xs, tbs, r.stream);
+    void* aux = nullptr;
+    if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
+    return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, r.stream);
+  };
   hipError_t e = hipSuccess;
   if (part == SscaPart::kStage1) {
-    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, hc, oc, r.batch, r.xs, r.os, r.stream);
+    e = stage1(ic, oc, r.batch, r.os);
   } else if (part == SscaPart::kStage2) {
     if (N == 1024) {
       // The Stage 1 output already is the result; copy it if the caller asked for another buffer.
@@ -272,7 +288,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     }
   } else if (per == 0) {
     // N == 1024: the Stage 1 output is the final result.
-    e = scd::launch_ssca_pass1_fp32(ic, n, Np, win, tabs, hc, oc, r.batch, r.xs, r.os, r.stream);
+    e = stage1(ic, oc, r.batch, r.os);
   } else {
     int chunk = r.batch;
     void* work = r.work;
@@ -284,10 +300,11 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     float2* T = static_cast<float2*>(work);
     for (int b0 = 0; b0 < r.batch && e == hipSuccess; b0 += chunk) {
       const int nb = std::min(chunk, r.batch - b0);
-      e = scd::launch_ssca_pass1_fp32(ic + b0 * r.xs, n, Np, win, tabs, hc, T, nb, r.xs, grid, r.stream);
+      e = stage1(ic + b0 * r.xs, T, nb, grid);
       if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc + b0 * r.os, nb, grid, r.os, r.stream);
     }
   }
+  if (e == hipErrorOutOfMemory) return SCD_ERR_NOMEM;
   if (e != hipSuccess) return hip_fail(e, "SSCA launch");
   return SCD_OK;
 }
@@ -374,6 +391,7 @@ void scd_shutdown(void) {
     (void)hipDeviceSynchronize();
     for (auto& p : kv.second.plans) (void)hipFree(p.second);
     if (kv.second.work) (void)hipFree(kv.second.work);
+    if (kv.second.aux) (void)hipFree(kv.second.aux);
   }
   (void)hipSetDevice(cur);
   g_dev.clear();

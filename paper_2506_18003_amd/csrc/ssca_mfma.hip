@@ -1,0 +1,323 @@
+// SSCA Stage 1 with the channelizer DFT on the matrix cores (MFMA), in split or plain 16-bit precision.
+//
+// The channel-subset DFT of Eq. (3) is a complex GEMM Y[frame][k'] = sum_j x[frame][j] W[j][k'] with
+// W[j][k'] = w[j] omega_Np^{(c + S k') j}. It is computed realified and transposed on
+// v_mfma_f32_32x32x16_{bf16,f16}: the 32 rows are the 16 channels' (re, im) outputs, the 32 columns are
+// frames and K = 2 Np runs over the frame's interleaved (re, im) samples:
+//   rows 2k'   : [ Re W, -Im W ] . [x_re, x_im]     rows 2k'+1 : [ Im W,  Re W ] . [x_re, x_im].
+// In the split forms both operands carry a hi and a lo 16-bit part (v = hi + lo, lo = v - hi rounded) and the
+// GEMM sums W_hi X_hi + W_hi X_lo + W_lo X_hi in FP32, which leaves an error of order 2^-16 (bf16) or 2^-22
+// (fp16) relative to the operands instead of the 2^-8 / 2^-11 of a single 16-bit product. The plain forms
+// (one product) exist as the accuracy ablation. The weights are generated in FP64 on the GPU before the split.
+//
+// Everything after the channelizer (down-conversion, channel-data product, the M1-point DFT, rotation, the
+// blocked store) is FP32 and organised as in the FP32 Stage 1 (see ssca_fp32.hip); only the frame <-> lane
+// mapping follows the MFMA output layout: lane l of wave w holds, for frames t' = 64 w + 32 u + (l mod 32)
+// (u < 2) of each 256-frame chunk, the 8 channels k' in {0,1,4,5,8,9,12,13} + 2 (l / 32).
+#include <type_traits>
+
+#include "scd_device.h"
+#include "scd_launch.h"
+
+namespace scd {
+
+namespace {
+
+constexpr int kM1 = 1024;
+constexpr int kThreads = 256;
+constexpr int kSeq = 256;
+constexpr int kSeqStride = kSeq + kSeq / 16;
+constexpr int kHalfSeqs = 32;
+constexpr int kXchgFloats = kHalfSeqs * kSeqStride;
+constexpr int kJS = 8;                   // complex samples per sub-chunk = one K-step of 16 reals
+constexpr int kRow = kJS + 4;            // LDS words per frame row (4 words of padding break bank conflicts)
+constexpr int kPlaneWords = kThreads * kRow;
+constexpr int kStageWords = 2 * kPlaneWords;  // hi and lo planes
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// The same 16 bytes when only 4-byte alignment is known (rows of the 16-bit copies of x start anywhere).
+typedef unsigned u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int PREC>
+struct Prec {
+  static constexpr bool kSplit = (PREC == SCD_PREC_SPLIT_BF16 || PREC == SCD_PREC_SPLIT_FP16);
+  static constexpr bool kBf16 = (PREC == SCD_PREC_SPLIT_BF16 || PREC == SCD_PREC_BF16);
+  using T16 = typename std::conditional<kBf16, __bf16, _Float16>::type;
+  using V8 = typename std::conditional<kBf16, bf16x8, f16x8>::type;
+  __device__ __forceinline__ static f32x16 mfma(V8 a, V8 b, f32x16 c) {
+    if constexpr (kBf16) return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T16>
+__device__ __forceinline__ unsigned short bits16(T16 v) {
+  return __builtin_bit_cast(unsigned short, v);
+}
+
+// x -> 16-bit hi and lo planes, one 32-bit word (re, im) per sample, with kMfmaPad zero samples on each side.
+template <int PREC>
+__global__ void split_x_kernel(const float2* __restrict__ x, int N, unsigned* __restrict__ hi,
+                               unsigned* __restrict__ lo) {
+  using P = Prec<PREC>;
+  using T16 = typename P::T16;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = e - kMfmaPad;
+  if (e >= N + 2 * kMfmaPad) return;
+  float2 v = make_float2(0.f, 0.f);
+  if (n >= 0 && n < N) v = x[n];
+  const T16 hr = static_cast<T16>(v.x), hm = static_cast<T16>(v.y);
+  const T16 lr = static_cast<T16>(v.x - static_cast<float>(hr)), lm = static_cast<T16>(v.y - static_cast<float>(hm));
+  hi[e] = bits16(hr) | (static_cast<unsigned>(bits16(hm)) << 16);
+  lo[e] = bits16(lr) | (static_cast<unsigned>(bits16(lm)) << 16);
+}
+
+// Realified, transposed channel-subset DFT weights in FP64, split into 16-bit hi and lo:
+// W[c][row][k] for row = 2 k' + comp, k = 2 j + xcomp, stored row-major with K = 2 Np.
+template <int PREC>
+__global__ void mfma_weights_kernel(const float* __restrict__ win, int Np, int S, unsigned short* __restrict__ whi,
+                                    unsigned short* __restrict__ wlo) {
+  using T16 = typename Prec<PREC>::T16;
+  const int K = 2 * Np;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * 32 * K) return;
+  const int c = e / (32 * K), row = (e / K) % 32, k = e % K;
+  const int kp = row >> 1, comp = row & 1, j = k >> 1, xcomp = k & 1;
+  const int ch = c + S * kp;
+  double s, co;
+  sincospi(-2.0 * static_cast<double>((ch * j) & (Np - 1)) / static_cast<double>(Np), &s, &co);
+  const double hr = static_cast<double>(win[j]) * co, hm = static_cast<double>(win[j]) * s;
+  const double v = (comp == 0) ? (xcomp == 0 ? hr : -hm) : (xcomp == 0 ? hm : hr);
+  const T16 h = static_cast<T16>(v);
+  whi[e] = bits16(h);
+  wlo[e] = bits16(static_cast<T16>(v - static_cast<double>(h)));
+}
+
+__device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
+  return cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
+}
+
+template <int NP, int PREC, bool PHASE_BY_M2>
+__global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __restrict__ x, int N, int M2,
+                                                              int m2shift, const unsigned* __restrict__ xhi,
+                                                              const unsigned* __restrict__ xlo,
+                                                              const unsigned short* __restrict__ whi_g,
+                                                              const unsigned short* __restrict__ wlo_g,
+                                                              const float2* __restrict__ tabs,
+                                                              float2* __restrict__ T, int64_t xbs, int64_t pbs,
+                                                              int64_t tbs) {
+  using P = Prec<PREC>;
+  using V8 = typename P::V8;
+  constexpr int S = NP / 16;
+  constexpr int D = NP / 2 - 1;
+  constexpr int K = 2 * NP;
+  constexpr int NSUB = NP / kJS;
+  constexpr int kStageFloats = kStageWords;  // one float2 slot per two words
+  constexpr int kBufFloats = kStageFloats > kXchgFloats ? kStageFloats : kXchgFloats;
+  __shared__ float2 buf[kBufFloats];
+  __shared__ float2 tw[1024];
+  __shared__ float2 stp[16];
+  __shared__ float2 rt[NP];
+  unsigned* words = reinterpret_cast<unsigned*>(buf);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, g = lane >> 5, lc = lane & 31;
+  const int nblk = gridDim.x;
+  int lin = blockIdx.x;
+  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
+  const int c = lin >> m2shift;
+  const int m2 = lin & (M2 - 1);
+  x += blockIdx.y * xbs;
+  xhi += blockIdx.y * pbs;
+  xlo += blockIdx.y * pbs;
+  T += blockIdx.y * tbs;
+  const float2* rlo = tabs + kTabRotLo;
+  const unsigned short* whi = whi_g + c * 32 * K;
+  const unsigned short* wlo = wlo_g + c * 32 * K;
+  const auto xr = make_rsrc(x, N * 8);
+  const int hishift = 10 - m2shift;
+
+  for (int i = tid; i < 1024; i += kThreads) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < NP; i += kThreads) rt[i] = tabs[kTabRoots + i];
+  if (tid < 16) stp[tid] = rot_factor(rlo, tabs + kTabTw1024, 64 * m2 * tid, hishift);
+
+  // Sub-chunk s: frames m1 = 256 (s / NSUB) + i (i < 256), samples kJS (s % NSUB) + [0, kJS). Each thread moves
+  // 4 x 16 bytes: (frame i, sample group q2 of 4, plane).
+  u32x4 pf[4];
+  auto issue = [&](int s) {
+    const int sbase = (256 * (s / NSUB)) * M2 + m2 - D + (s % NSUB) * kJS + kMfmaPad;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + kThreads * q;  // 0 .. 1023
+      const int i = e >> 2, q2 = (e >> 1) & 1, plane = e & 1;
+      const unsigned* src = (plane ? xlo : xhi) + sbase + i * M2 + 4 * q2;
+      pf[q] = *reinterpret_cast<const u32x4_a4*>(src);
+    }
+  };
+  auto stash = [&](int s) {
+    unsigned* b = words + (s & 1) * kStageWords;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + kThreads * q;
+      const int i = e >> 2, q2 = (e >> 1) & 1, plane = e & 1;
+      *reinterpret_cast<u32x4*>(b + plane * kPlaneWords + i * kRow + 4 * q2) = pf[q];
+    }
+  };
+  issue(0);
+  stash(0);
+  issue(1);
+
+  float2 col[4][2][8];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    f32x16 acc[2] = {};
+#pragma unroll 1
+    for (int sub = 0; sub < NSUB; ++sub) {
+      const int s = f * NSUB + sub;
+      __syncthreads();
+      // Weight operand: row lc, K range 16 sub + 8 g .. +8.
+      const V8 wh = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(whi + lc * K + 16 * sub + 8 * g));
+      V8 wl;
+      if constexpr (P::kSplit) wl = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(wlo + lc * K + 16 * sub + 8 * g));
+      const unsigned* b = words + (s & 1) * kStageWords;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int fr = 64 * wave + 32 * u + lc;
+        const V8 xh = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(b + fr * kRow + 4 * g));
+        acc[u] = P::mfma(wh, xh, acc[u]);
+        if constexpr (P::kSplit) {
+          const V8 xl = __builtin_bit_cast(V8, *reinterpret_cast<const u32x4*>(b + kPlaneWords + fr * kRow + 4 * g));
+          acc[u] = P::mfma(wh, xl, acc[u]);
+          acc[u] = P::mfma(wl, xh, acc[u]);
+        }
+      }
+      if (s + 1 < 4 * NSUB) stash(s + 1);
+      if (s + 2 < 4 * NSUB) issue(s + 2);
+    }
+    // acc[u][r]: row 8 (r/4) + 4 g + r%4 of frame 64 w + 32 u + lc; rows 2k' (re), 2k'+1 (im).
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int n = (64 * wave + 32 * u + lc + 256 * f) * M2 + m2;
+      const float2 xn = load_c64(xr, n);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float2 y = make_float2(acc[u][2 * q], acc[u][2 * q + 1]);
+        if constexpr (PHASE_BY_M2) {
+          col[f][u][q] = cmulc(y, xn);
+        } else {
+          const int kp = 4 * (q >> 1) + 2 * g + (q & 1);
+          col[f][u][q] = cmul(y, cmulc(rt[((c + S * kp) * n) & (NP - 1)], xn));
+        }
+      }
+    }
+  }
+
+  // 4-point DFT over f and twiddle omega_1024^{t' r}.
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int tp = 64 * wave + 32 * u + lc;
+    const float2 t1 = tw[tp], t2 = tw[2 * tp], t3 = tw[3 * tp];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float2 a[4] = {col[0][u][q], col[1][u][q], col[2][u][q], col[3][u][q]};
+      dft4(a);
+      col[0][u][q] = a[0];
+      col[1][u][q] = cmul(a[1], t1);
+      col[2][u][q] = cmul(a[2], t2);
+      col[3][u][q] = cmul(a[3], t3);
+    }
+  }
+
+  // Two exchanges: half h holds the 8 channels of lane group g == h as sequences b = 4 q + r.
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if (g == h) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int tp = 64 * wave + 32 * u + lc;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) buf[(q * 4 + r) * kSeqStride + tp + (tp >> 4)] = col[r][u][q];
+        }
+      }
+    }
+    __syncthreads();
+    auto st = [&](int b, int m, float2 v) {
+      const int q = b >> 2;
+      const int kp = 4 * (q >> 1) + 2 * h + (q & 1);
+      const int k = c + S * kp;
+      const int rj = (b & 3) + 4 * (m & 15);
+      float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
+      if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
+      const int i = m >> 4;
+      st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+    };
+    NoLoad ld;
+    lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
+  }
+}
+
+template <int NP, int PREC>
+hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, void* scratch,
+                 float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+  constexpr int S = NP / 16;
+  const int64_t plane = N + 2 * kMfmaPad;
+  unsigned* xhi = static_cast<unsigned*>(scratch);
+  unsigned* xlo = xhi + plane * batch;
+  unsigned short* whi = reinterpret_cast<unsigned short*>(xlo + plane * batch);
+  unsigned short* wlo = whi + S * 32 * 2 * NP;
+  const int nw = S * 32 * 2 * NP;
+  hipLaunchKernelGGL(mfma_weights_kernel<PREC>, dim3((nw + 255) / 256), dim3(256), 0, s, win, NP, S, whi, wlo);
+  for (int b = 0; b < batch; ++b)
+    hipLaunchKernelGGL(split_x_kernel<PREC>, dim3((plane + 255) / 256), dim3(256), 0, s, x + b * xbs, N,
+                       xhi + b * plane, xlo + b * plane);
+  dim3 grid(M2 * S, batch);
+  if (M2 % NP == 0)
+    hipLaunchKernelGGL((ssca_pass1_mfma<NP, PREC, true>), grid, dim3(kThreads), 0, s, x, N, M2, m2shift, xhi, xlo,
+                       whi, wlo, tabs, T, xbs, plane, tbs);
+  else
+    hipLaunchKernelGGL((ssca_pass1_mfma<NP, PREC, false>), grid, dim3(kThreads), 0, s, x, N, M2, m2shift, xhi, xlo,
+                       whi, wlo, tabs, T, xbs, plane, tbs);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t pass1_np(const float2* x, int N, int Np, const float* win, const float2* tabs, void* scratch, float2* T,
+                    int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+  const int M2 = N / kM1;
+  int m2shift = 0;
+  while ((1 << m2shift) < M2) ++m2shift;
+  switch (Np) {
+    case 16: return pass1<16, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case 32: return pass1<32, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case 64: return pass1<64, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case 128: return pass1<128, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t ssca_mfma_scratch_bytes(int N, int Np, int batch) {
+  const size_t plane = static_cast<size_t>(N) + 2 * kMfmaPad;
+  const size_t S = static_cast<size_t>(Np) / 16;
+  return 2 * 4 * plane * static_cast<size_t>(batch) + 2 * 2 * S * 32 * 2 * static_cast<size_t>(Np);
+}
+
+hipError_t launch_ssca_pass1_mfma(int prec, const float2* x, int N, int Np, const float* win, const float2* tabs,
+                                  void* scratch, float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+  switch (prec) {
+    case SCD_PREC_SPLIT_BF16: return pass1_np<SCD_PREC_SPLIT_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case SCD_PREC_SPLIT_FP16: return pass1_np<SCD_PREC_SPLIT_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case SCD_PREC_BF16: return pass1_np<SCD_PREC_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case SCD_PREC_FP16: return pass1_np<SCD_PREC_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace scd

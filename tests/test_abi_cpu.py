@@ -107,3 +107,9 @@ def test_workspace_size(L):
     assert L.scd_fam_workspace_size(256, 64, 256, 16, ctypes.byref(v)) == 0
     assert v.value == 8 * 256 * 256 * 16
     assert L.scd_ssca_workspace_size(1024, 64, 1, None) == _lib.SCD_ERR_NULL
+
+
+def test_split_precision_np256_unsupported(L):
+    o = _lib.ScdOpts()
+    o.precision = _lib.PRECISIONS["split_bf16"]
+    assert L.scd_ssca_ex(_fake(X), 4096, 256, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED

@@ -188,3 +188,42 @@ def test_nonsymmetric_window(dev):
     assert rel(S, O.ssca(f64(x), Np, w.astype(np.float64))) <= TOL_FP32
     F = scd.fam(to_gpu(x[:1024], dev), Np, 8, 128, win=torch.from_numpy(w).to(dev)).cpu().numpy()
     assert rel(F, O.fam(f64(x[:1024]), Np, 8, 128, w.astype(np.float64))) <= TOL_FP32
+
+
+TOL_SPLIT = 1e-3
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("N,Np", [(1024, 32), (2048, 16), (1 << 14, 64), (1 << 16, 64), (8192, 128)])
+def test_ssca_split_precision(dev, prec, N, Np):
+    x = sg.qpsk(N, 0.13, 6, 4.0, sg.rng_for(60, N + Np))
+    w = w32(Np)
+    S = scd.ssca(to_gpu(x, dev), Np, win=torch.from_numpy(w).to(dev), precision=prec).cpu().numpy()
+    assert rel(S, O.ssca(f64(x), Np, w.astype(np.float64))) <= TOL_SPLIT
+
+
+def test_ssca_split_bf16_cfg3_full_size(dev):
+    """The headline workload in split-BF16: sampled strips against the FP64 oracle, error <= 1e-3 of peak,
+    and the unsplit BF16 ablation measurably worse."""
+    c = W.cfg3()
+    x, p = c["x"], c["ssca"]
+    w = w32(p["Np"])
+    xg, wg = to_gpu(x, dev), torch.from_numpy(w).to(dev)
+    S = scd.ssca(xg, p["Np"], win=wg, precision="split_bf16")
+    S1 = scd.ssca(xg, p["Np"], win=wg, precision="bf16")
+    xf = f64(x)
+    strips = (0, 6, 13, 51)
+    refs = {k: O.ssca_strip(xf, p["Np"], w.astype(np.float64), k) for k in strips}
+    peak = max(np.abs(r).max() for r in refs.values())
+    e_split = max(np.abs(S[k].cpu().numpy() - refs[k]).max() for k in strips) / peak
+    e_plain = max(np.abs(S1[k].cpu().numpy() - refs[k]).max() for k in strips) / peak
+    assert e_split <= TOL_SPLIT
+    assert e_plain > 10 * e_split
+
+
+def test_ssca_split_batch(dev):
+    N, Np, B = 1 << 14, 128, 3
+    xs = np.stack([sg.bpsk(N, 0.04 * (b + 1), 5, 0.0, sg.rng_for(61, b)) for b in range(B)])
+    S = scd.ssca(to_gpu(xs, dev), Np, precision="split_bf16").cpu().numpy()
+    for b in range(B):
+        assert rel(S[b], O.ssca(f64(xs[b]), Np, w32(Np).astype(np.float64))) <= TOL_SPLIT, b
