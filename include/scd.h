@@ -147,6 +147,78 @@ int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out);
 /* scd_fam with options (batch, strides, stream, workspace for X_T). Only SCD_FP32 is supported. */
 int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
 
+/* ---------------------------------------------------------------------------------------------------------
+ * Learned strip selection. The paper has no learned component (its glossary only names the averaged cyclic
+ * periodogram and the PSD, and its conclusion points at a machine-learning back-end); the definitions below
+ * are this library's. A small MLP reads per-strip features and predicts which SSCA strips carry cycle-frequency
+ * energy; only those strips then get their N-point DFT, with the full SSCA as fallback below a confidence
+ * threshold.
+ *
+ * Features (2 Np floats per signal, strip k): from the SSCAs S_b of 16 segments of 1024 samples starting at
+ * b N/16 (each zero outside itself), A_k[q] = sum_b |S_b[k][q]|^2;
+ *   feat[k]      = 0.5 log(A_k[q0(k)]) centred over k, q0(k) = (-k_c 1024/Np) mod 1024 (alpha = 0 bin);
+ *   feat[Np + k] = log(max / mean of A_k over bins more than 2 bins (circularly) away from q0(k)).
+ * Labels (from a full SSCA): strip k is active when max |S[k][q]|^2 > (6.2^2 / 2) * mean |S[k][q]|^2 over the
+ * bins q whose cycle frequency is at least 8/N away from 0 modulo 1.
+ * MLP: f -> relu(W1 f + b1) -> relu(W2 h1 + b2) -> sigmoid(W3 h2 + b3), sizes 2 Np -> 256 -> 256 -> Np, on
+ * standardised features (f - mu) / sigma. Parameters are one FP32 device array packed as
+ * [W1 (256 x 2Np) | b1 (256) | W2 (256 x 256) | b2 (256) | W3 (Np x 256) | b3 (Np)], W row-major [out][in];
+ * every GEMM rounds both operands to bf16 and accumulates in FP32 on the matrix cores.
+ * ------------------------------------------------------------------------------------------------------- */
+
+/* A trained selector. All arrays are device memory owned by the caller. */
+typedef struct scd_selector {
+  int Np;              /* channel count the model was trained for                         */
+  const float* params; /* packed MLP parameters, scd_mlp_param_count(Np) floats            */
+  const float* mu;     /* feature means, 2 Np floats                                       */
+  const float* sigma;  /* feature scales, 2 Np floats                                      */
+  float theta;         /* strip score threshold                                            */
+  float conf_min;      /* fall back to the full SSCA when min_k max(s_k, 1 - s_k) < conf_min */
+} scd_selector;
+
+/* Number of packed MLP parameters for Np channels (262912 for Np = 256), or SCD_ERR_SIZE. */
+int scd_mlp_param_count(int Np);
+
+/* Features of each signal: x device [batch] signals of N (power of two in [2^14, 2^20]) at opts->x_stride,
+ * feat device [batch][2 Np]. Uses library-owned scratch (16 * Np * 8 KiB). */
+int scd_features(const float* x, int64_t N, int Np, const float* win, float* feat, const scd_opts* opts);
+
+/* Labels of each strip of densely packed SCDs S (device [batch][Np][N] complex, as written by scd_ssca):
+ * labels device [batch][Np] (0 or 1), ratio device [batch][Np] (max / mean, may be NULL). */
+int scd_strip_labels(const float* S, int64_t N, int Np, float* labels, float* ratio, const scd_opts* opts);
+
+/* out[i][j] = (f[i][j] - mu[j]) / sigma[j] for n rows of dim (device arrays). stream: hipStream_t or NULL. */
+int scd_standardize(const float* f, const float* mu, const float* sigma, float* out, int n, int dim, void* stream);
+
+/* MLP forward pass on `batch` standardised feature rows x (device [batch][2 Np]). act (device,
+ * [4][batch][256]) receives the pre- and post-activation of both hidden layers (a1, h1, a2, h2), z (device
+ * [batch][Np]) the logits and scores (device [batch][Np]) the sigmoid outputs. */
+int scd_mlp_forward(int Np, int batch, const float* params, const float* x, float* act, float* z, float* scores,
+                    void* stream);
+
+/* Gradients of the mean binary cross-entropy between scores and labels (device [batch][Np]) with respect to the
+ * packed parameters (grads, device, packed like params) and, if dx is not NULL, to x (device [batch][2 Np]).
+ * act and scores come from scd_mlp_forward on the same x; scratch is device memory of
+ * batch * (Np + 512) floats. */
+int scd_mlp_backward(int Np, int batch, const float* params, const float* x, const float* act, const float* scores,
+                     const float* labels, float* grads, float* scratch, float* dx, void* stream);
+
+/* One Adam step (step number t >= 1) on n parameters in place; m and v are the moment estimates. */
+int scd_adam_step(int n, float* params, const float* grads, float* m, float* v, int t, float lr, float beta1,
+                  float beta2, float eps, void* stream);
+
+/* mask[b][k] = scores[b][k] >= theta; conf[b] = min_k max(s, 1 - s) (device arrays). */
+int scd_select(const float* scores, int Np, int batch, float theta, unsigned char* mask, float* conf, void* stream);
+
+/* SSCA of one signal restricted to the strips the selector picks. Runs the features, the MLP and the selection
+ * on the GPU, reads the mask and confidence back (this call synchronises its stream once), then computes and
+ * writes only the selected strips of out ([Np][N]; the other rows are left untouched). If the confidence is
+ * below selector->conf_min the full SSCA runs instead, *fell_back is set to 1 and mask is set to all ones.
+ * mask: device Np bytes (written). fell_back: host int. opts: precision (SCD_FP32 or SCD_SPLIT_BF16), stream,
+ * workspace as scd_ssca_ex (batch must be 1). N must be a power of two in [2^14, 2^20]. Errors as scd_ssca_ex, plus SCD_ERR_MODEL. */
+int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
+                     unsigned char* mask, int* fell_back, const scd_opts* opts);
+
 /* Bytes of workspace scd_ssca_ex needs for `batch` signals (0 when N == 1024). Errors: SCD_ERR_NULL,
  * SCD_ERR_SIZE. */
 int scd_ssca_workspace_size(int64_t N, int Np, int batch, size_t* bytes);

@@ -44,6 +44,17 @@ class ScdOpts(ctypes.Structure):
     ]
 
 
+class ScdSelector(ctypes.Structure):
+    _fields_ = [
+        ("Np", ctypes.c_int),
+        ("params", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
+        ("theta", ctypes.c_float),
+        ("conf_min", ctypes.c_float),
+    ]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -59,6 +70,17 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_size_t)]),
     "scd_fam_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_size_t)]),
+    "scd_mlp_param_count": (ctypes.c_int, [ctypes.c_int]),
+    "scd_features": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
+    "scd_strip_labels": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
+    "scd_standardize": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "scd_mlp_forward": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "scd_mlp_backward": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "scd_adam_step": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, _P]),
+    "scd_select": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float, _P, _P, _P]),
+    "scd_ssca_learned": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ScdOpts)]),
     "scd_set_stream": (ctypes.c_int, [_P]),
     "scd_last_error": (ctypes.c_char_p, []),
     "scd_version": (ctypes.c_int, []),

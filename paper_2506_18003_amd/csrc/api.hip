@@ -27,7 +27,14 @@ struct DevState {
   size_t work_bytes = 0;
   void* aux = nullptr;  // 16-bit copies of x and MFMA weights of the split-precision channelizer
   size_t aux_bytes = 0;
+  void* lrn = nullptr;  // segment SSCAs of the selector features
+  size_t lrn_bytes = 0;
+  void* sel = nullptr;  // selector scratch: features, activations, scores, confidence
+  size_t sel_bytes = 0;
 };
+// features (2 Np) + standardised features (2 Np) + activations (4 * 256) + logits (Np) + scores (Np) + conf
+constexpr int kSelStructFloats = (sizeof(scd::ChanSel) + 3) / 4 + 4;
+constexpr int kSelScratchFloats = 4 * 256 + 4 * 256 + 2 * 256 + 64 + kSelStructFloats;
 std::map<int, DevState> g_dev;
 
 int fail(int code, const char* fmt, ...) {
@@ -140,6 +147,7 @@ int grow(void** buf, size_t* have, size_t bytes, void** out) {
 
 int get_work(DevState& st, size_t bytes, void** out) { return grow(&st.work, &st.work_bytes, bytes, out); }
 int get_aux(DevState& st, size_t bytes, void** out) { return grow(&st.aux, &st.aux_bytes, bytes, out); }
+int get_lrn(DevState& st, size_t bytes, void** out) { return grow(&st.lrn, &st.lrn_bytes, bytes, out); }
 
 int current_device(int* dev) {
   hipError_t e = hipGetDevice(dev);
@@ -154,8 +162,6 @@ struct Resolved {
   hipStream_t stream = nullptr;
   void* work = nullptr;
   size_t work_bytes = 0;
-  void* aux = nullptr;  // 16-bit copies of x and MFMA weights of the split-precision channelizer
-  size_t aux_bytes = 0;
 };
 
 int resolve(const scd_opts* o, int64_t xlen, int64_t olen, Resolved* r) {
@@ -225,7 +231,7 @@ enum class SscaPart { kWhole, kStage1, kStage2 };
 // Shared validation and dispatch of the SSCA entry points. For kStage1 `in` is x and `dst` the intermediate;
 // for kStage2 `in` is the intermediate and `dst` the output (win unused); for kWhole `in` is x and `dst` out.
 int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* win, float* dst,
-                const scd_opts* opts) {
+                const scd_opts* opts, const scd::SelArg* selp = nullptr) {
   const bool need_win = part != SscaPart::kStage2;
   if (!in || !dst || (need_win && !win)) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
   if (!is_pow2(N) || N < 1024 || N > (1 << 20))
@@ -267,12 +273,13 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   float2* oc = reinterpret_cast<float2*>(dst);
   const int n = static_cast<int>(N);
   const int prec = r.precision;
+  const scd::SelArg sel = selp ? *selp : scd::selarg_all(Np);
   // Stage 1 in the requested precision, for nb signals.
   auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
-    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, hc, T, nb, r.xs, tbs, r.stream);
+    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, hc, T, nb, r.xs, tbs, sel, r.stream);
     void* aux = nullptr;
     if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
-    return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, r.stream);
+    return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, sel, r.stream);
   };
   hipError_t e = hipSuccess;
   if (part == SscaPart::kStage1) {
@@ -284,7 +291,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
         e = hipMemcpyAsync(oc + b * r.os, ic + b * r.xs, 8u * static_cast<size_t>(grid), hipMemcpyDeviceToDevice,
                            r.stream);
     } else {
-      e = scd::launch_ssca_pass2(ic, n, Np, tabs, oc, r.batch, r.xs, r.os, r.stream);
+      e = scd::launch_ssca_pass2(ic, n, Np, tabs, oc, r.batch, r.xs, r.os, sel, r.stream);
     }
   } else if (per == 0) {
     // N == 1024: the Stage 1 output is the final result.
@@ -301,7 +308,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     for (int b0 = 0; b0 < r.batch && e == hipSuccess; b0 += chunk) {
       const int nb = std::min(chunk, r.batch - b0);
       e = stage1(ic + b0 * r.xs, T, nb, grid);
-      if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc + b0 * r.os, nb, grid, r.os, r.stream);
+      if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc + b0 * r.os, nb, grid, r.os, sel, r.stream);
     }
   }
   if (e == hipErrorOutOfMemory) return SCD_ERR_NOMEM;
@@ -381,6 +388,182 @@ int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out) 
   return scd_fam_ex(x, Np, L, P, win, out, nullptr);
 }
 
+int scd_mlp_param_count(int Np) {
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  return scd::mlp_layout(Np).total;
+}
+
+int scd_features(const float* x, int64_t N, int Np, const float* win, float* feat, const scd_opts* opts) {
+  if (!x || !win || !feat) return fail(SCD_ERR_NULL, "x, win and feat must be non-NULL");
+  if (!is_pow2(N) || N < (1 << 14) || N > (1 << 20))
+    return fail(SCD_ERR_SIZE, "features need N a power of two in [2^14, 2^20] (got %lld)", static_cast<long long>(N));
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  Resolved r;
+  int rc = resolve(opts, N, 2 * Np, &r);
+  if (rc) return rc;
+  if (r.work) return fail(SCD_ERR_UNSUPPORTED, "scd_features uses library-owned scratch only");
+  std::lock_guard<std::mutex> lk(g_mu);
+  const size_t xb = span_bytes(r.batch, r.xs, N);
+  if ((rc = check_device_range(x, xb, "x"))) return rc;
+  if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
+  if ((rc = check_device_range(feat, 4u * static_cast<size_t>(2 * Np) * r.batch, "feat"))) return rc;
+  int dev;
+  if ((rc = current_device(&dev))) return rc;
+  DevState& st = g_dev[dev];
+  float2* tabs;
+  if ((rc = get_tables(st, 1024, Np, r.stream, &tabs))) return rc;
+  const size_t segb = 8u * 16u * static_cast<size_t>(Np) * 1024u;
+  void* lrn;
+  if ((rc = get_lrn(st, segb, &lrn))) return rc;
+  float2* seg = static_cast<float2*>(lrn);
+  const scd::SelArg sel = scd::selarg_all(Np);
+  const float2* xc = reinterpret_cast<const float2*>(x);
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < r.batch && e == hipSuccess; ++b) {
+    // 16 segments of 1024 samples, each an SSCA of its own (zero outside the segment).
+    e = scd::launch_ssca_pass1_fp32(xc + b * r.xs, 1024, Np, win, tabs, tabs + scd::kTabSize, seg, 16, N / 16,
+                                    static_cast<int64_t>(Np) * 1024, sel, r.stream);
+    if (e == hipSuccess) e = scd::launch_acp_features(seg, Np, 1, feat + static_cast<size_t>(b) * 2 * Np, r.stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "feature launch");
+  return SCD_OK;
+}
+
+int scd_strip_labels(const float* S, int64_t N, int Np, float* labels, float* ratio, const scd_opts* opts) {
+  if (!S || !labels) return fail(SCD_ERR_NULL, "S and labels must be non-NULL");
+  if (!is_pow2(N) || N < 1024 || N > (1 << 20)) return fail(SCD_ERR_SIZE, "N must be a power of two in [2^10, 2^20]");
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
+  Resolved r;
+  int rc = resolve(opts, static_cast<int64_t>(Np) * N, Np, &r);
+  if (rc) return rc;
+  if (r.xs != static_cast<int64_t>(Np) * N) return fail(SCD_ERR_SIZE, "labels need densely packed SCDs");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((rc = check_device_range(S, 8u * static_cast<size_t>(Np) * N * r.batch, "S"))) return rc;
+  if ((rc = check_device_range(labels, 4u * static_cast<size_t>(Np) * r.batch, "labels"))) return rc;
+  if (ratio && (rc = check_device_range(ratio, 4u * static_cast<size_t>(Np) * r.batch, "ratio"))) return rc;
+  hipError_t e = scd::launch_labels(reinterpret_cast<const float2*>(S), N, Np, r.batch, labels, ratio, r.stream);
+  if (e != hipSuccess) return hip_fail(e, "label launch");
+  return SCD_OK;
+}
+
+int scd_standardize(const float* f, const float* mu, const float* sigma, float* out, int n, int dim, void* stream) {
+  if (!f || !mu || !sigma || !out) return fail(SCD_ERR_NULL, "NULL argument");
+  if (n < 1 || dim < 1) return fail(SCD_ERR_SIZE, "n and dim must be positive");
+  hipError_t e = scd::launch_standardize(f, mu, sigma, out, n, dim, stream ? static_cast<hipStream_t>(stream) : g_stream);
+  if (e != hipSuccess) return hip_fail(e, "standardize launch");
+  return SCD_OK;
+}
+
+int scd_mlp_forward(int Np, int batch, const float* params, const float* x, float* act, float* z, float* scores,
+                    void* stream) {
+  if (!params || !x || !act || !z || !scores) return fail(SCD_ERR_NULL, "NULL argument");
+  if (!is_pow2(Np) || Np < 16 || Np > 256 || batch < 1) return fail(SCD_ERR_SIZE, "bad Np or batch");
+  hipError_t e = scd::launch_mlp_forward(Np, batch, params, x, act, z, scores,
+                                         stream ? static_cast<hipStream_t>(stream) : g_stream);
+  if (e != hipSuccess) return hip_fail(e, "MLP forward launch");
+  return SCD_OK;
+}
+
+int scd_mlp_backward(int Np, int batch, const float* params, const float* x, const float* act, const float* scores,
+                     const float* labels, float* grads, float* scratch, float* dx, void* stream) {
+  if (!params || !x || !act || !scores || !labels || !grads || !scratch) return fail(SCD_ERR_NULL, "NULL argument");
+  if (!is_pow2(Np) || Np < 16 || Np > 256 || batch < 1) return fail(SCD_ERR_SIZE, "bad Np or batch");
+  hipError_t e = scd::launch_mlp_backward(Np, batch, params, x, act, scores, labels, grads, scratch, dx,
+                                          stream ? static_cast<hipStream_t>(stream) : g_stream);
+  if (e != hipSuccess) return hip_fail(e, "MLP backward launch");
+  return SCD_OK;
+}
+
+int scd_adam_step(int n, float* params, const float* grads, float* m, float* v, int t, float lr, float beta1,
+                  float beta2, float eps, void* stream) {
+  if (!params || !grads || !m || !v) return fail(SCD_ERR_NULL, "NULL argument");
+  if (n < 1 || t < 1) return fail(SCD_ERR_SIZE, "n and t must be positive");
+  hipError_t e = scd::launch_adam(params, grads, m, v, n, t, lr, beta1, beta2, eps,
+                                  stream ? static_cast<hipStream_t>(stream) : g_stream);
+  if (e != hipSuccess) return hip_fail(e, "Adam launch");
+  return SCD_OK;
+}
+
+int scd_select(const float* scores, int Np, int batch, float theta, unsigned char* mask, float* conf, void* stream) {
+  if (!scores || !mask || !conf) return fail(SCD_ERR_NULL, "NULL argument");
+  if (!is_pow2(Np) || Np < 16 || Np > 256 || batch < 1) return fail(SCD_ERR_SIZE, "bad Np or batch");
+  hipError_t e = scd::launch_select(scores, Np, batch, theta, mask, conf,
+                                    stream ? static_cast<hipStream_t>(stream) : g_stream);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  return SCD_OK;
+}
+
+int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
+                     unsigned char* mask, int* fell_back, const scd_opts* opts) {
+  if (!x || !win || !selector || !out || !mask || !fell_back) return fail(SCD_ERR_NULL, "NULL argument");
+  if (!selector->params || !selector->mu || !selector->sigma) return fail(SCD_ERR_MODEL, "selector has NULL arrays");
+  if (selector->Np != Np) return fail(SCD_ERR_MODEL, "selector was trained for Np = %d, not %d", selector->Np, Np);
+  if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_learned takes one signal per call");
+  if (opts && opts->precision != SCD_FP32 && opts->precision != SCD_SPLIT_BF16)
+    return fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
+  if (!is_pow2(N) || N < (1 << 14) || N > (1 << 20))
+    return fail(SCD_ERR_SIZE, "the learned form needs N a power of two in [2^14, 2^20]");
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
+  hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
+  // Selector scratch: features, standardised features, activations, logits, scores, confidence.
+  const scd::MlpLayout L = scd::mlp_layout(Np);
+  int rc;
+  float* f = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev;
+    if ((rc = current_device(&dev))) return rc;
+    if ((rc = check_device_range(selector->params, 4u * L.total, "selector params"))) return rc;
+    if ((rc = check_device_range(selector->mu, 8u * Np, "selector mu"))) return rc;
+    if ((rc = check_device_range(selector->sigma, 8u * Np, "selector sigma"))) return rc;
+    if ((rc = check_device_range(mask, static_cast<size_t>(Np), "mask"))) return rc;
+    void* p;
+    if ((rc = grow(&g_dev[dev].sel, &g_dev[dev].sel_bytes, 4u * kSelScratchFloats, &p))) return rc;
+    f = static_cast<float*>(p);
+  }
+  float* fs = f + 2 * Np;
+  float* act = fs + 2 * Np;
+  float* z = act + 4 * scd::kHidden;
+  float* sc = z + Np;
+  float* conf = sc + Np;
+  scd_opts fo{};
+  fo.stream = stream;
+  if ((rc = scd_features(x, N, Np, win, f, &fo))) return rc;
+  hipError_t e = scd::launch_standardize(f, selector->mu, selector->sigma, fs, 1, 2 * Np, stream);
+  if (e == hipSuccess) e = scd::launch_mlp_forward(Np, 1, selector->params, fs, act, z, sc, stream);
+  if (e == hipSuccess) e = scd::launch_select(sc, Np, 1, selector->theta, mask, conf, stream);
+  unsigned char hmask[256];
+  float hconf = 0.f;
+  if (e == hipSuccess) e = hipMemcpyAsync(hmask, mask, Np, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hconf, conf, 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "selector");
+  scd::ChanSel hsel;
+  if (hconf < selector->conf_min) {
+    *fell_back = 1;
+    std::memset(hmask, 1, Np);
+    e = hipMemcpyAsync(mask, hmask, Np, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "mask update");
+    hsel = scd::chansel_all(Np);
+  } else {
+    *fell_back = 0;
+    hsel = scd::chansel_from_mask(Np, hmask);
+    if (hsel.nch == 0) return SCD_OK;
+  }
+  // The selection goes to device memory (after the selector scratch), where the kernels read it.
+  scd::ChanSel* dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
+  e = hipMemcpyAsync(dsel, &hsel, sizeof(hsel), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "selection upload");
+  const scd::SelArg sel{dsel, hsel.nsub, hsel.nch};
+  scd_opts so{};
+  if (opts) so = *opts;
+  so.batch = 1;
+  so.stream = stream;
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, &so, &sel);
+}
+
 void scd_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_dev.empty()) return;
@@ -392,6 +575,8 @@ void scd_shutdown(void) {
     for (auto& p : kv.second.plans) (void)hipFree(p.second);
     if (kv.second.work) (void)hipFree(kv.second.work);
     if (kv.second.aux) (void)hipFree(kv.second.aux);
+    if (kv.second.lrn) (void)hipFree(kv.second.lrn);
+    if (kv.second.sel) (void)hipFree(kv.second.sel);
   }
   (void)hipSetDevice(cur);
   g_dev.clear();

@@ -20,6 +20,26 @@ constexpr int SCD_PREC_BF16 = 3;
 constexpr int SCD_PREC_FP16 = 4;
 constexpr int kMfmaPad = 256;  // zero samples on each side of the 16-bit copies of x
 
+// Which strips an SSCA launch computes (passed by value as a kernel argument). Stage 1 runs the channel
+// subsets sub[0..nsub) and stores strip k only if bit k of keep is set; stage 2 runs strips ch[0..nch).
+struct ChanSel {
+  unsigned keep[8];
+  unsigned char sub[16];
+  unsigned char ch[256];
+  int nsub, nch;
+};
+// Every strip of an Np-channel SSCA.
+ChanSel chansel_all(int Np);
+// The strips with mask[k] != 0 (host array of Np bytes).
+ChanSel chansel_from_mask(int Np, const unsigned char* mask);
+// A selection as the launchers take it: the counts (host) and the ChanSel in device memory, read by the kernels
+// through the scalar cache; dev == nullptr means every strip (sub[i] = i, ch[k] = k, all kept).
+struct SelArg {
+  const ChanSel* dev;
+  int nsub, nch;
+};
+inline SelArg selarg_all(int Np) { return SelArg{nullptr, Np / 16, Np}; }
+
 hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 
 // SSCA Stage 1 (channelizer + CDP + M1-point DFT + rotation) of `batch` signals. x: [batch][N] at stride xbs;
@@ -27,22 +47,46 @@ hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 // intermediate layout equals the output layout [Np][N]. hc: kHcFloats float2 of device scratch that this call
 // fills with the subsets' complex windows before stage 1 reads them.
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
-                                  float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t stream);
+                                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel,
+                                  hipStream_t stream);
 
 // SSCA Stage 1 with the channelizer on MFMA in 16-bit (split or plain) precision, Np <= 128. scratch: device
 // memory of ssca_mfma_scratch_bytes(N, Np, batch) bytes for the 16-bit copies of x and the DFT weights,
 // filled by this call. Other arguments as launch_ssca_pass1_fp32.
 size_t ssca_mfma_scratch_bytes(int N, int Np, int batch);
 hipError_t launch_ssca_pass1_mfma(int prec, const float2* x, int N, int Np, const float* win, const float2* tabs,
-                                  void* scratch, float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t stream);
+                                  void* scratch, float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel,
+                                  hipStream_t stream);
 
 // SSCA Stage 2 (M2-point DFT over m2) of `batch` intermediates into out: [batch][Np][N] at stride obs. A no-op
 // when N == 1024.
 hipError_t launch_ssca_pass2(const float2* T, int N, int Np, const float2* tabs, float2* out, int batch,
-                             int64_t tbs, int64_t obs, hipStream_t stream);
+                             int64_t tbs, int64_t obs, const SelArg& sel, hipStream_t stream);
 
 // FAM of `batch` signals. x: [batch][P*L] at stride xbs; xt: [batch][Np][P] scratch; out: [batch][Np][Np][P].
 hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs,
                            float2* xt, float2* out, int batch, int64_t xbs, int64_t obs, hipStream_t stream);
+
+// ---- learned strip selector (learn.hip) ----
+constexpr int kHidden = 256;
+struct MlpLayout {  // offsets (floats) of the packed parameters [W1 b1 W2 b2 W3 b3]
+  int in, out, W1, b1, W2, b2, W3, b3, total;
+};
+MlpLayout mlp_layout(int Np);
+// seg: [nsig][16][Np][1024] segment SSCAs -> feat [nsig][2 Np] (centred PSD, ACP).
+hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t stream);
+// S: [nsig][Np][N] -> labels [nsig][Np] (0/1), ratio [nsig][Np] (may be null).
+hipError_t launch_labels(const float2* S, int64_t N, int Np, int nsig, float* labels, float* ratio,
+                         hipStream_t stream);
+hipError_t launch_standardize(const float* f, const float* mu, const float* sigma, float* out, int n, int dim,
+                              hipStream_t stream);
+hipError_t launch_mlp_forward(int Np, int B, const float* params, const float* x, float* act, float* z, float* sc,
+                              hipStream_t stream);
+hipError_t launch_mlp_backward(int Np, int B, const float* params, const float* x, const float* act, const float* sc,
+                               const float* y, float* grads, float* scratch, float* dx, hipStream_t stream);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int t, float lr, float b1, float b2,
+                       float eps, hipStream_t stream);
+hipError_t launch_select(const float* sc, int Np, int nsig, float theta, unsigned char* mask, float* conf,
+                         hipStream_t stream);
 
 }  // namespace scd

@@ -58,11 +58,12 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 // in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its last radix stage stores to HBM, multiplying by
 // the rotation factor omega_N^{m2 m1'} (and by the down-conversion factor omega_Np^{(k m2) mod Np}, which
 // does not depend on m1 when Np divides M2), built per butterfly as a base times a per-block step table.
-template <int NP, bool PHASE_BY_M2>
+template <int NP, bool PHASE_BY_M2, bool SEL>
 __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* __restrict__ x, int N, int M2,
                                                                 int m2shift, const float2* __restrict__ hcg,
                                                                 const float2* __restrict__ tabs,
-                                                                float2* __restrict__ T, int64_t xbs, int64_t tbs) {
+                                                                float2* __restrict__ T, int64_t xbs, int64_t tbs,
+                                                                const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
   constexpr int D = NP / 2 - 1;
   constexpr int JS = NP < 16 ? NP : 16;  // samples per sub-chunk
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
   const int nblk = gridDim.x;
   int lin = blockIdx.x;
   if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
-  const int c = lin >> m2shift;
+  const int c = SEL ? sel->sub[lin >> m2shift] : (lin >> m2shift);
   const int m2 = lin & (M2 - 1);
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
       float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
       if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
       const int i = m >> 4;
-      st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
+        st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
@@ -244,12 +246,12 @@ template <int M2>
 __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __restrict__ T,
                                                              const float2* __restrict__ tabs,
                                                              float2* __restrict__ out, int N, int64_t tbs,
-                                                             int64_t obs) {
+                                                             int64_t obs, const ChanSel* __restrict__ sel) {
   __shared__ float2 buf[M2 * 16];
   __shared__ float2 tw[1024];
   const int tid = threadIdx.x;
   const int mb = blockIdx.x;  // block of 16 consecutive m1'
-  const int k = blockIdx.y;
+  const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
   __syncthreads();
   const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (M2 * 16);
@@ -259,58 +261,93 @@ __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __re
 
 template <int NP>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* hc,
-                 float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+                 float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   constexpr int S = NP / 16;
+  if (sel.nsub <= 0) return hipSuccess;
   hipLaunchKernelGGL(ssca_hc_kernel, dim3((S * NP + 255) / 256), dim3(256), 0, s, win, tabs, hc, NP, S);
-  dim3 grid(M2 * S, batch);
-  if (M2 % NP == 0)
-    hipLaunchKernelGGL((ssca_pass1_fp32<NP, true>), grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T,
-                       xbs, tbs);
-  else
-    hipLaunchKernelGGL((ssca_pass1_fp32<NP, false>), grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T,
-                       xbs, tbs);
+  dim3 grid(M2 * sel.nsub, batch);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T, xbs, tbs, sel.dev);
+  };
+  if (M2 % NP == 0) {
+    if (sel.dev) go(ssca_pass1_fp32<NP, true, true>);
+    else go(ssca_pass1_fp32<NP, true, false>);
+  } else {
+    if (sel.dev) go(ssca_pass1_fp32<NP, false, true>);
+    else go(ssca_pass1_fp32<NP, false, false>);
+  }
   return hipGetLastError();
 }
 
 template <int M2>
-hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int Np, int batch, int64_t tbs,
-                 int64_t obs, hipStream_t s) {
-  dim3 grid(kM1 / 16, Np, batch);
-  hipLaunchKernelGGL(ssca_pass2_fp32<M2>, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs);
+hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int batch, int64_t tbs, int64_t obs,
+                 const SelArg& sel, hipStream_t s) {
+  if (sel.nch <= 0) return hipSuccess;
+  dim3 grid(kM1 / 16, sel.nch, batch);
+  hipLaunchKernelGGL(ssca_pass2_fp32<M2>, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
   return hipGetLastError();
 }
 
 }  // namespace
 
+ChanSel chansel_all(int Np) {
+  ChanSel c{};
+  for (int k = 0; k < Np; ++k) {
+    c.keep[k >> 5] |= 1u << (k & 31);
+    c.ch[k] = static_cast<unsigned char>(k);
+  }
+  const int S = Np / 16;
+  for (int i = 0; i < S; ++i) c.sub[i] = static_cast<unsigned char>(i);
+  c.nsub = S;
+  c.nch = Np;
+  return c;
+}
+
+ChanSel chansel_from_mask(int Np, const unsigned char* mask) {
+  ChanSel c{};
+  const int S = Np / 16;
+  bool used[16] = {};
+  for (int k = 0; k < Np; ++k) {
+    if (!mask[k]) continue;
+    c.keep[k >> 5] |= 1u << (k & 31);
+    c.ch[c.nch++] = static_cast<unsigned char>(k);
+    used[k % S] = true;  // strip k belongs to subset k mod S
+  }
+  for (int i = 0; i < S; ++i)
+    if (used[i]) c.sub[c.nsub++] = static_cast<unsigned char>(i);
+  return c;
+}
+
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
-                                  float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+                                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
-    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
-    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
-    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
-    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, s);
+    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
+    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
+    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
+    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
+    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_ssca_pass2(const float2* T, int N, int Np, const float2* tabs, float2* out, int batch, int64_t tbs,
-                             int64_t obs, hipStream_t s) {
+                             int64_t obs, const SelArg& sel, hipStream_t s) {
+  (void)Np;
   switch (N / kM1) {
     case 1: return hipSuccess;
-    case 2: return pass2<2>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 4: return pass2<4>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 8: return pass2<8>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 16: return pass2<16>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 32: return pass2<32>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 64: return pass2<64>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 128: return pass2<128>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 256: return pass2<256>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 512: return pass2<512>(T, tabs, out, N, Np, batch, tbs, obs, s);
-    case 1024: return pass2<1024>(T, tabs, out, N, Np, batch, tbs, obs, s);
+    case 2: return pass2<2>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 4: return pass2<4>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 8: return pass2<8>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 16: return pass2<16>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 32: return pass2<32>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 64: return pass2<64>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 128: return pass2<128>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 256: return pass2<256>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 512: return pass2<512>(T, tabs, out, N, batch, tbs, obs, sel, s);
+    case 1024: return pass2<1024>(T, tabs, out, N, batch, tbs, obs, sel, s);
     default: return hipErrorInvalidValue;
   }
 }

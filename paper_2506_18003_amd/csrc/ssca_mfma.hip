@@ -100,7 +100,7 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
   return cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
 }
 
-template <int NP, int PREC, bool PHASE_BY_M2>
+template <int NP, int PREC, bool PHASE_BY_M2, bool SEL>
 __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __restrict__ x, int N, int M2,
                                                               int m2shift, const unsigned* __restrict__ xhi,
                                                               const unsigned* __restrict__ xlo,
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
                                                               const unsigned short* __restrict__ wlo_g,
                                                               const float2* __restrict__ tabs,
                                                               float2* __restrict__ T, int64_t xbs, int64_t pbs,
-                                                              int64_t tbs) {
+                                                              int64_t tbs, const ChanSel* __restrict__ sel) {
   using P = Prec<PREC>;
   using V8 = typename P::V8;
   constexpr int S = NP / 16;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
   const int nblk = gridDim.x;
   int lin = blockIdx.x;
   if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
-  const int c = lin >> m2shift;
+  const int c = SEL ? sel->sub[lin >> m2shift] : (lin >> m2shift);
   const int m2 = lin & (M2 - 1);
   x += blockIdx.y * xbs;
   xhi += blockIdx.y * pbs;
@@ -255,7 +255,8 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
       float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
       if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
       const int i = m >> 4;
-      st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
+        st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
@@ -264,8 +265,9 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
 
 template <int NP, int PREC>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, void* scratch,
-                 float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+                 float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   constexpr int S = NP / 16;
+  if (sel.nsub <= 0) return hipSuccess;
   const int64_t plane = N + 2 * kMfmaPad;
   unsigned* xhi = static_cast<unsigned*>(scratch);
   unsigned* xlo = xhi + plane * batch;
@@ -276,27 +278,36 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
   for (int b = 0; b < batch; ++b)
     hipLaunchKernelGGL(split_x_kernel<PREC>, dim3((plane + 255) / 256), dim3(256), 0, s, x + b * xbs, N,
                        xhi + b * plane, xlo + b * plane);
-  dim3 grid(M2 * S, batch);
-  if (M2 % NP == 0)
-    hipLaunchKernelGGL((ssca_pass1_mfma<NP, PREC, true>), grid, dim3(kThreads), 0, s, x, N, M2, m2shift, xhi, xlo,
-                       whi, wlo, tabs, T, xbs, plane, tbs);
-  else
-    hipLaunchKernelGGL((ssca_pass1_mfma<NP, PREC, false>), grid, dim3(kThreads), 0, s, x, N, M2, m2shift, xhi, xlo,
-                       whi, wlo, tabs, T, xbs, plane, tbs);
+  dim3 grid(M2 * sel.nsub, batch);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, s, x, N, M2, m2shift, xhi, xlo, whi, wlo, tabs, T, xbs, plane,
+                       tbs, sel.dev);
+  };
+  // Strip selection (learned form) is built for the split-bf16 channelizer only.
+  if (sel.dev && PREC != SCD_PREC_SPLIT_BF16) return hipErrorInvalidValue;
+  if constexpr (PREC == SCD_PREC_SPLIT_BF16) {
+    if (sel.dev) {
+      if (M2 % NP == 0) go(ssca_pass1_mfma<NP, PREC, true, true>);
+      else go(ssca_pass1_mfma<NP, PREC, false, true>);
+      return hipGetLastError();
+    }
+  }
+  if (M2 % NP == 0) go(ssca_pass1_mfma<NP, PREC, true, false>);
+  else go(ssca_pass1_mfma<NP, PREC, false, false>);
   return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t pass1_np(const float2* x, int N, int Np, const float* win, const float2* tabs, void* scratch, float2* T,
-                    int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+                    int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case 32: return pass1<32, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case 64: return pass1<64, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case 128: return pass1<128, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case 16: return pass1<16, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case 32: return pass1<32, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case 64: return pass1<64, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case 128: return pass1<128, PREC>(x, N, M2, m2shift, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -310,12 +321,13 @@ size_t ssca_mfma_scratch_bytes(int N, int Np, int batch) {
 }
 
 hipError_t launch_ssca_pass1_mfma(int prec, const float2* x, int N, int Np, const float* win, const float2* tabs,
-                                  void* scratch, float2* T, int batch, int64_t xbs, int64_t tbs, hipStream_t s) {
+                                  void* scratch, float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel,
+                                  hipStream_t s) {
   switch (prec) {
-    case SCD_PREC_SPLIT_BF16: return pass1_np<SCD_PREC_SPLIT_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case SCD_PREC_SPLIT_FP16: return pass1_np<SCD_PREC_SPLIT_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case SCD_PREC_BF16: return pass1_np<SCD_PREC_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
-    case SCD_PREC_FP16: return pass1_np<SCD_PREC_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, s);
+    case SCD_PREC_SPLIT_BF16: return pass1_np<SCD_PREC_SPLIT_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case SCD_PREC_SPLIT_FP16: return pass1_np<SCD_PREC_SPLIT_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case SCD_PREC_BF16: return pass1_np<SCD_PREC_BF16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
+    case SCD_PREC_FP16: return pass1_np<SCD_PREC_FP16>(x, N, Np, win, tabs, scratch, T, batch, xbs, tbs, sel, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,241 @@
+"""Learned strip selection: features, labels, the MLP selector and its GPU training loop.
+
+Thin layer over the selector entry points of include/scd.h (scd_features, scd_strip_labels,
+scd_mlp_forward/backward, scd_adam_step, scd_select, scd_ssca_learned). torch tensors hold the device arrays;
+every numerical step runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+from . import _lib
+
+HIDDEN = 256
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(t):
+    return _torch().cuda.current_stream(t.device).cuda_stream
+
+
+def _opts(x, batch, x_stride=0, out_stride=0):
+    o = _lib.ScdOpts()
+    o.batch = batch
+    o.x_stride = x_stride
+    o.out_stride = out_stride
+    o.stream = _stream(x)
+    return o
+
+
+def param_count(Np: int) -> int:
+    n = _lib.lib().scd_mlp_param_count(Np)
+    if n < 0:
+        _lib.check(n)
+    return n
+
+
+def layout(Np: int) -> dict:
+    """Offsets of the packed parameters [W1 b1 W2 b2 W3 b3]."""
+    o = {}
+    off = 0
+    for name, size in (("W1", HIDDEN * 2 * Np), ("b1", HIDDEN), ("W2", HIDDEN * HIDDEN), ("b2", HIDDEN),
+                       ("W3", Np * HIDDEN), ("b3", Np)):
+        o[name] = (off, size)
+        off += size
+    return o
+
+
+def features(x, Np: int, win=None):
+    """Selector features [B, 2 Np] of each signal in x (complex64 CUDA, [N] or [B, N], N >= 2^14)."""
+    torch = _torch()
+    from . import _window, _check_x
+    _check_x(x)
+    N = x.shape[-1]
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    feat = torch.empty(B, 2 * Np, dtype=torch.float32, device=x.device)
+    o = _opts(x, B, x.stride(0) if x.dim() == 2 else 0)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_features(x.data_ptr(), N, Np, w.data_ptr(), feat.data_ptr(), ctypes.byref(o)))
+    return feat
+
+
+def strip_labels(S):
+    """(labels, ratio) [B, Np] of densely packed SCDs S ([Np, N] or [B, Np, N] complex64 CUDA)."""
+    torch = _torch()
+    Np, N = S.shape[-2], S.shape[-1]
+    B = 1 if S.dim() == 2 else S.shape[0]
+    lab = torch.empty(B, Np, dtype=torch.float32, device=S.device)
+    ratio = torch.empty(B, Np, dtype=torch.float32, device=S.device)
+    o = _opts(S, B)
+    with torch.cuda.device(S.device):
+        _lib.check(_lib.lib().scd_strip_labels(S.data_ptr(), N, Np, lab.data_ptr(), ratio.data_ptr(), ctypes.byref(o)))
+    return lab, ratio
+
+
+def standardize(f, mu, sigma):
+    torch = _torch()
+    out = torch.empty_like(f)
+    with torch.cuda.device(f.device):
+        _lib.check(_lib.lib().scd_standardize(f.data_ptr(), mu.data_ptr(), sigma.data_ptr(), out.data_ptr(),
+                                              f.shape[0], f.shape[1], _stream(f)))
+    return out
+
+
+def mlp_forward(params, x, Np):
+    """(act, z, s): act [4, B, 256] = (a1, h1, a2, h2), logits z and scores s [B, Np]."""
+    torch = _torch()
+    B = x.shape[0]
+    act = torch.empty(4, B, HIDDEN, dtype=torch.float32, device=x.device)
+    z = torch.empty(B, Np, dtype=torch.float32, device=x.device)
+    s = torch.empty(B, Np, dtype=torch.float32, device=x.device)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_mlp_forward(Np, B, params.data_ptr(), x.data_ptr(), act.data_ptr(), z.data_ptr(),
+                                              s.data_ptr(), _stream(x)))
+    return act, z, s
+
+
+def mlp_backward(params, x, act, s, y, Np, want_dx=False):
+    """(grads packed like params, dx or None) of the mean BCE loss."""
+    torch = _torch()
+    B = x.shape[0]
+    grads = torch.empty_like(params)
+    scratch = torch.empty(B * (Np + 2 * HIDDEN), dtype=torch.float32, device=x.device)
+    dx = torch.empty_like(x) if want_dx else None
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_mlp_backward(Np, B, params.data_ptr(), x.data_ptr(), act.data_ptr(), s.data_ptr(),
+                                               y.data_ptr(), grads.data_ptr(), scratch.data_ptr(),
+                                               dx.data_ptr() if dx is not None else None, _stream(x)))
+    return grads, dx
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    torch = _torch()
+    with torch.cuda.device(params.device):
+        _lib.check(_lib.lib().scd_adam_step(params.numel(), params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                                            v.data_ptr(), t, lr, b1, b2, eps, _stream(params)))
+
+
+def select(scores, theta):
+    """(mask [B, Np] uint8, conf [B])."""
+    torch = _torch()
+    B, Np = scores.shape
+    mask = torch.empty(B, Np, dtype=torch.uint8, device=scores.device)
+    conf = torch.empty(B, dtype=torch.float32, device=scores.device)
+    with torch.cuda.device(scores.device):
+        _lib.check(_lib.lib().scd_select(scores.data_ptr(), Np, B, float(theta), mask.data_ptr(), conf.data_ptr(),
+                                         _stream(scores)))
+    return mask, conf
+
+
+def init_params(Np: int, seed: int = 0):
+    """He-initialised packed parameters (numpy float32), zero biases."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(param_count(Np), np.float32)
+    for name, (off, size) in layout(Np).items():
+        if name.startswith("W"):
+            fan_in = {"W1": 2 * Np, "W2": HIDDEN, "W3": HIDDEN}[name]
+            out[off:off + size] = rng.standard_normal(size) * np.sqrt(2.0 / fan_in)
+    return out
+
+
+class Selector:
+    """A trained selector: packed parameters, feature standardisation, score threshold and confidence floor."""
+
+    def __init__(self, Np, params, mu, sigma, theta=0.5, conf_min=0.9, meta=None):
+        self.Np = Np
+        self.params = params
+        self.mu = mu
+        self.sigma = sigma
+        self.theta = float(theta)
+        self.conf_min = float(conf_min)
+        self.meta = meta or {}
+
+    def to(self, device):
+        torch = _torch()
+        cast = lambda a: torch.as_tensor(np.asarray(a.cpu() if hasattr(a, "cpu") else a, np.float32), device=device)
+        return Selector(self.Np, cast(self.params), cast(self.mu), cast(self.sigma), self.theta, self.conf_min,
+                        self.meta)
+
+    def scores(self, feat):
+        x = standardize(feat, self.mu, self.sigma)
+        return mlp_forward(self.params, x, self.Np)[2]
+
+    def save(self, path):
+        np.savez(path, params=np.asarray(self.params.cpu() if hasattr(self.params, "cpu") else self.params),
+                 mu=np.asarray(self.mu.cpu() if hasattr(self.mu, "cpu") else self.mu),
+                 sigma=np.asarray(self.sigma.cpu() if hasattr(self.sigma, "cpu") else self.sigma))
+        with open(os.path.splitext(path)[0] + ".json", "w") as fh:
+            json.dump(dict(Np=self.Np, theta=self.theta, conf_min=self.conf_min, meta=self.meta), fh, indent=1)
+
+    @staticmethod
+    def load(path, device=None):
+        d = np.load(path)  # arrays written by Selector.save; no pickled objects
+        with open(os.path.splitext(path)[0] + ".json") as fh:
+            m = json.load(fh)
+        sel = Selector(m["Np"], d["params"], d["mu"], d["sigma"], m["theta"], m["conf_min"], m.get("meta"))
+        return sel.to(device) if device is not None else sel
+
+    def c_struct(self):
+        c = _lib.ScdSelector()
+        c.Np = self.Np
+        c.params = self.params.data_ptr()
+        c.mu = self.mu.data_ptr()
+        c.sigma = self.sigma.data_ptr()
+        c.theta = self.theta
+        c.conf_min = self.conf_min
+        return c
+
+
+def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None):
+    """SSCA of one signal restricted to the strips the selector picks: (out, mask [Np] uint8, fell_back)."""
+    torch = _torch()
+    from . import _window, _check_x, PRECISIONS
+    _check_x(x)
+    N = x.shape[-1]
+    Np = sel.Np
+    w = _window(win, Np, x.device)
+    if out is None:
+        out = torch.zeros(Np, N, dtype=torch.complex64, device=x.device)
+    mask = torch.empty(Np, dtype=torch.uint8, device=x.device)
+    fb = ctypes.c_int(0)
+    o = _lib.ScdOpts()
+    o.precision = PRECISIONS[precision]
+    o.stream = _stream(x)
+    cs = sel.c_struct()
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_learned(x.data_ptr(), N, Np, w.data_ptr(), ctypes.byref(cs), out.data_ptr(),
+                                               mask.data_ptr(), ctypes.byref(fb), ctypes.byref(o)))
+    return out, mask, bool(fb.value)
+
+
+class Trainer:
+    """Mini-batch BCE training of the selector MLP with Adam, entirely in the library's GPU kernels."""
+
+    def __init__(self, Np, device, seed=0, lr=1e-3):
+        torch = _torch()
+        self.Np = Np
+        self.params = torch.as_tensor(init_params(Np, seed), device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.lr = lr
+
+    def step(self, x, y):
+        """One Adam step on standardised features x [B, 2 Np] and labels y [B, Np]; returns the batch scores."""
+        act, _, s = mlp_forward(self.params, x, self.Np)
+        g, _ = mlp_backward(self.params, x, act, s, y, self.Np)
+        self.t += 1
+        adam_step(self.params, g, self.m, self.v, self.t, lr=self.lr)
+        return s
+
+    def state(self):
+        return dict(params=self.params, m=self.m, v=self.v, t=self.t)

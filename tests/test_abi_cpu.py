@@ -113,3 +113,20 @@ def test_split_precision_np256_unsupported(L):
     o = _lib.ScdOpts()
     o.precision = _lib.PRECISIONS["split_bf16"]
     assert L.scd_ssca_ex(_fake(X), 4096, 256, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
+
+
+def test_learned_entry_errors(L):
+    assert L.scd_mlp_param_count(256) == 262912
+    assert L.scd_mlp_param_count(100) == _lib.SCD_ERR_SIZE
+    v = ctypes.c_size_t()
+    assert L.scd_features(None, 1 << 14, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_NULL
+    assert L.scd_features(_fake(X), 1 << 12, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    sel = _lib.ScdSelector()
+    sel.Np = 64
+    fb = ctypes.c_int()
+    assert L.scd_ssca_learned(_fake(X), 1 << 16, 64, _fake(W), ctypes.byref(sel), _fake(O), _fake(O + 8),
+                              ctypes.byref(fb), None) == _lib.SCD_ERR_MODEL
+    sel.params, sel.mu, sel.sigma = 0x1000, 0x2000, 0x3000
+    assert L.scd_ssca_learned(_fake(X), 1 << 16, 32, _fake(W), ctypes.byref(sel), _fake(O), _fake(O + 8),
+                              ctypes.byref(fb), None) == _lib.SCD_ERR_MODEL
+    assert L.scd_adam_step(0, _fake(X), _fake(W), _fake(O), _fake(O), 1, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.SCD_ERR_SIZE

@@ -2,7 +2,8 @@
 
 * Every out-of-range-safe sample load is one 64-bit buffer load with the whole offset in the range-checked
   VGPR operand; a split or narrowed load would read past the signal instead of the zero padding.
-* The headline Stage-1 kernel (Np = 64, Np dividing M2) and the Stage-2 kernels do not spill registers.
+* The headline Stage-1 kernel (Np = 64, Np dividing M2, all strips) and the Stage-2 kernels do not spill
+  registers.
 """
 import os
 import re
@@ -50,7 +51,7 @@ def _spills(asm):
 
 def test_hot_kernels_do_not_spill(asm):
     sp = _spills(asm)
-    hot = [n for n in sp if "ssca_pass1_fp32ILi64ELb1E" in n or "ssca_pass2_fp32" in n]
+    hot = [n for n in sp if "ssca_pass1_fp32ILi64ELb1ELb0E" in n or "ssca_pass2_fp32" in n]
     assert any("pass1" in n for n in hot) and any("pass2" in n for n in hot)
     for n in hot:
         assert sp[n] == 0, n

@@ -1,0 +1,164 @@
+"""GPU parity of the learned strip selector against its FP64 reference (oracle/learn_ref.py)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2506_18003_amd as scd  # noqa: E402
+from paper_2506_18003_amd import selector as SEL  # noqa: E402
+from oracle import learn_ref as LR  # noqa: E402
+from oracle import scd_oracle as O  # noqa: E402
+from synth import signals as sg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def f64(x):
+    return np.asarray(x).astype(np.complex64).astype(np.complex128)
+
+
+def gpu(x, dev, dtype=torch.complex64):
+    return torch.as_tensor(np.ascontiguousarray(x), device=dev).to(dtype)
+
+
+@pytest.mark.parametrize("N,Np", [(1 << 14, 16), (1 << 15, 64), (1 << 14, 256)])
+def test_features_match_reference(dev, N, Np):
+    xs = [sg.bpsk(N, 0.08, 6, 8.0, sg.rng_for(80, N + Np)), sg.noise(N, sg.rng_for(80, 1 + Np))]
+    w = sg.hamming(Np).astype(np.float32)
+    F = SEL.features(gpu(np.stack(xs), dev), Np, win=torch.from_numpy(w).to(dev)).cpu().numpy()
+    for b, x in enumerate(xs):
+        ref = LR.features(f64(x), Np, w.astype(np.float64))
+        assert np.abs(F[b] - ref).max() <= 2e-3, b
+
+
+def test_labels_match_reference(dev):
+    N, Np = 8192, 32
+    xs = [sg.bpsk(N, 0.1, 4, 15.0, sg.rng_for(81, 0)), sg.noise(N, sg.rng_for(81, 1)),
+          sg.qpsk(N, 0.2, 8, 3.0, sg.rng_for(81, 2))]
+    S = scd.ssca(gpu(np.stack(xs), dev), Np)
+    lab, ratio = SEL.strip_labels(S)
+    lab, ratio = lab.cpu().numpy(), ratio.cpu().numpy()
+    for b, x in enumerate(xs):
+        rl, rr = LR.labels_from_scd(O.ssca(f64(x), Np, sg.hamming(Np).astype(np.float32).astype(np.float64)))
+        assert np.allclose(ratio[b], rr, rtol=1e-3), b
+        clear = np.abs(rr - LR.T_LABEL) > 1e-2 * LR.T_LABEL   # decisions away from the threshold must agree
+        assert np.array_equal(lab[b][clear], rl[clear]), b
+
+
+def _params_dict(p, Np):
+    out = {}
+    for name, (off, size) in SEL.layout(Np).items():
+        a = p[off:off + size].astype(np.float64)
+        if name == "W1":
+            a = a.reshape(SEL.HIDDEN, 2 * Np)
+        elif name == "W2":
+            a = a.reshape(SEL.HIDDEN, SEL.HIDDEN)
+        elif name == "W3":
+            a = a.reshape(Np, SEL.HIDDEN)
+        out[name] = a
+    return out
+
+
+@pytest.mark.parametrize("Np,B", [(16, 37), (64, 70)])
+def test_mlp_forward_backward_match_bf16_reference(dev, Np, B):
+    """Both sides round every GEMM operand to bf16; the remaining differences come from FP32 vs FP64
+    accumulation (an operand that lands within one bf16 ulp of a rounding boundary may round differently)."""
+    rng = np.random.default_rng(Np + B)
+    p = SEL.init_params(Np, seed=3)
+    p[SEL.layout(Np)["b1"][0]:][:SEL.HIDDEN] = rng.standard_normal(SEL.HIDDEN) * 0.1
+    X = rng.standard_normal((B, 2 * Np)).astype(np.float32)
+    Y = (rng.random((B, Np)) > 0.6).astype(np.float32)
+    pg, Xg, Yg = gpu(p, dev, torch.float32), gpu(X, dev, torch.float32), gpu(Y, dev, torch.float32)
+    act, z, s = SEL.mlp_forward(pg, Xg, Np)
+    grads, dx = SEL.mlp_backward(pg, Xg, act, s, Yg, Np, want_dx=True)
+    P = _params_dict(p, Np)
+    cache = LR.mlp_forward(P, X.astype(np.float64), bf16=True)
+    assert np.abs(s.cpu().numpy() - cache["s"]).max() <= 5e-3
+    g = LR.mlp_backward(P, X.astype(np.float64), Y.astype(np.float64), cache, bf16=True)
+    gg = _params_dict(grads.cpu().numpy(), Np)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        num = np.linalg.norm(gg[name] - g[name])
+        assert num <= 2e-2 * np.linalg.norm(g[name]) + 1e-9, name
+    assert np.linalg.norm(dx.cpu().numpy() - g["F"]) <= 2e-2 * np.linalg.norm(g["F"])
+
+
+def test_adam_matches_reference(dev):
+    rng = np.random.default_rng(5)
+    n = 1000
+    p, m, v = rng.standard_normal(n), np.zeros(n), np.zeros(n)
+    pg, mg, vg = (gpu(a, dev, torch.float32) for a in (p, m, v))
+    for t in range(1, 4):
+        gr = rng.standard_normal(n)
+        SEL.adam_step(pg, gpu(gr, dev, torch.float32), mg, vg, t, lr=1e-2)
+        p, m, v = LR.adam_step(p, gr, m, v, t, lr=1e-2)
+    assert np.allclose(pg.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_select_mask_and_confidence(dev):
+    s = np.array([[0.95, 0.02, 0.5, 0.99], [0.97, 0.01, 0.03, 0.92]] * 1, np.float32)
+    s = np.tile(s, (1, 4))
+    mask, conf = SEL.select(gpu(s, dev, torch.float32), 0.4)
+    assert np.array_equal(mask.cpu().numpy(), (s >= 0.4).astype(np.uint8))
+    assert np.allclose(conf.cpu().numpy(), np.minimum.reduce(np.maximum(s, 1 - s), axis=1))
+
+
+def test_training_lowers_loss(dev):
+    """A learnable rule (strip active when its ACP-like feature is positive) is fitted by the GPU loop."""
+    Np, B = 16, 256
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((B, 2 * Np)).astype(np.float32)
+    Y = (X[:, Np:] > 0.3).astype(np.float32)
+    tr = SEL.Trainer(Np, dev, seed=1, lr=3e-3)
+    Xg, Yg = gpu(X, dev, torch.float32), gpu(Y, dev, torch.float32)
+    first = None
+    for it in range(150):
+        s = tr.step(Xg, Yg)
+        if it == 0:
+            first = LR.bce(s.cpu().numpy().astype(np.float64), Y)
+    last = LR.bce(SEL.mlp_forward(tr.params, Xg, Np)[2].cpu().numpy().astype(np.float64), Y)
+    assert last < 0.3 * first
+
+
+def _fixed_selector(Np, keep, dev):
+    """A selector whose output ignores the features: strip k scores sigmoid(+-12) by keep[k]."""
+    p = np.zeros(SEL.param_count(Np), np.float32)
+    off, size = SEL.layout(Np)["b3"]
+    p[off:off + size] = np.where(keep, 12.0, -12.0)
+    return SEL.Selector(Np, p, np.zeros(2 * Np, np.float32), np.ones(2 * Np, np.float32), 0.5, 0.9).to(dev)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_learned_ssca_selected_strips_equal_full(dev, prec):
+    N, Np = 1 << 16, 64
+    x = gpu(sg.qpsk(N, 0.1, 8, 5.0, sg.rng_for(82, 0)), dev)
+    keep = np.zeros(Np, bool)
+    keep[[0, 3, 17, 18, 40, 63]] = True
+    sel = _fixed_selector(Np, keep, dev)
+    sentinel = torch.full((Np, N), complex(7.0, -7.0), dtype=torch.complex64, device=dev)
+    out, mask, fb = SEL.ssca_learned(x, sel, precision=prec, out=sentinel.clone())
+    assert not fb
+    assert np.array_equal(mask.cpu().numpy().astype(bool), keep)
+    full = scd.ssca(x, Np, precision=prec)
+    k = torch.from_numpy(np.nonzero(keep)[0]).to(dev)
+    nk = torch.from_numpy(np.nonzero(~keep)[0]).to(dev)
+    assert torch.equal(out[k], full[k])
+    assert torch.equal(out[nk], sentinel[nk])
+
+
+def test_learned_ssca_fallback_forced(dev):
+    N, Np = 1 << 14, 32
+    x = gpu(sg.bpsk(N, 0.1, 8, 5.0, sg.rng_for(83, 0)), dev)
+    keep = np.zeros(Np, bool)
+    keep[:3] = True
+    sel = _fixed_selector(Np, keep, dev)
+    sel.conf_min = 1.0  # no selector output can be that confident: forces the full SSCA
+    out, mask, fb = SEL.ssca_learned(x, sel)
+    assert fb and int(mask.sum()) == Np
+    assert torch.equal(out, scd.ssca(x, Np))
