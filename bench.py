@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16")
+    ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -95,6 +95,29 @@ def main():
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
+    learned_info = None
+    if "learned" in forms:
+        from paper_2506_18003_amd import selector as SEL
+
+        forms.remove("learned")
+        model = os.path.join(ROOT, "paper_2506_18003_amd", "models", f"selector_np{Np}.npz")
+        sel = SEL.Selector.load(model, dev)
+        lout = torch.zeros(Np, N, dtype=torch.complex64, device=dev)
+        for _ in range(args.warmup):
+            SEL.ssca_learned(x, sel, win=win, out=lout)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, mask, fb = SEL.ssca_learned(x, sel, win=win, out=lout)
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t0) * 1e3 / args.steps
+        m = mask.cpu().numpy().astype(bool)
+        full = scd.ssca(x, Np, win=win)
+        labels = SEL.strip_labels(full)[0].cpu().numpy()[0] > 0.5
+        recall = float((m & labels).sum() / max(1, labels.sum()))
+        learned_info = dict(ms_per_step=lms, strips=int(m.sum()), fell_back=bool(fb), recall_vs_full=recall,
+                            active_strips=int(labels.sum()), out=lout.cpu().numpy(), mask=m)
+        del full
     for form in forms:
         for _ in range(args.warmup):
             scd.ssca_stage1(x, Np, inter, win=win, precision=form)
@@ -155,6 +178,11 @@ def main():
         for form, rr in results.items():
             errs[form] = float(np.abs(rr["out"] - ref).max() / peak)
 
+        if learned_info is not None:
+            m = learned_info["mask"]
+            errs["learned"] = (float(np.abs(learned_info["out"][m] - ref[m]).max() / np.abs(ref[m]).max())
+                               if m.any() else None)
+
     value = Np * N / (r["ms_per_step"] * 1e-3)
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "SCD pts/s", "n_gpus": 1, "steps": args.steps,
@@ -173,6 +201,15 @@ def main():
                                           if "fp32" in results else None),
                       "max_err_vs_oracle": errs.get(f)} for f, rr in results.items()},
     }
+    if learned_info is not None:
+        li = learned_info
+        line["forms"]["learned"] = {
+            "pts_per_s": round(Np * N / (li["ms_per_step"] * 1e-3), 1), "ms_per_step": round(li["ms_per_step"], 5),
+            "speedup_vs_fp32": round(r["ms_per_step"] / li["ms_per_step"], 3), "strips_computed": li["strips"],
+            "selected_pts_per_s": round(li["strips"] * N / (li["ms_per_step"] * 1e-3), 1),
+            "fell_back": li["fell_back"], "active_strips": li["active_strips"],
+            "recall_vs_full": li["recall_vs_full"], "max_err_vs_oracle": errs.get("learned"),
+            "note": "whole scd_ssca_learned call: features, MLP, selection (one readback), selected strips"}
     print(json.dumps(line), flush=True)
 
 

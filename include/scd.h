@@ -157,9 +157,9 @@ int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* ou
  * Features (2 Np floats per signal, strip k): from the SSCAs S_b of 16 segments of 1024 samples starting at
  * b N/16 (each zero outside itself), A_k[q] = sum_b |S_b[k][q]|^2;
  *   feat[k]      = 0.5 log(A_k[q0(k)]) centred over k, q0(k) = (-k_c 1024/Np) mod 1024 (alpha = 0 bin);
- *   feat[Np + k] = log(max / mean of A_k over bins more than 2 bins (circularly) away from q0(k)).
+ *   feat[Np + k] = log(max / mean of A_k over bins more than 4 bins (circularly) away from q0(k)).
  * Labels (from a full SSCA): strip k is active when max |S[k][q]|^2 > (6.2^2 / 2) * mean |S[k][q]|^2 over the
- * bins q whose cycle frequency is at least 8/N away from 0 modulo 1.
+ * bins q whose cycle frequency is at least 1/256 away from 0 modulo 1.
  * MLP: f -> relu(W1 f + b1) -> relu(W2 h1 + b2) -> sigmoid(W3 h2 + b3), sizes 2 Np -> 256 -> 256 -> Np, on
  * standardised features (f - mu) / sigma. Parameters are one FP32 device array packed as
  * [W1 (256 x 2Np) | b1 (256) | W2 (256 x 256) | b2 (256) | W3 (Np x 256) | b3 (Np)], W row-major [out][in];

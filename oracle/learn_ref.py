@@ -12,11 +12,15 @@ Features of a signal of length N (2 Np values):
   q0(k)      = (-k_c N_C / Np) mod N_C, the alpha = 0 bin of strip k.
   PSD_k      = 0.5 log(A_k[q0(k)] + 1e-30), then centred: PSD_k - mean_k PSD_k.
   ACP_k      = log(max_{q not in guard} A_k[q] / mean_{q not in guard} A_k[q]), guard = bins with circular
-             distance <= 2 from q0(k).
+             distance <= 4 from q0(k) (|alpha| <= 1/256).
 Labels from the full SSCA S[k][q] (length N):
-  off(k)     = bins with |(q + k_c N / Np) wrapped to [-N/2, N/2)| >= 8, i.e. alpha at least 8/N away from
-             0 modulo 1 (a discrete-time signal's cycle frequencies are defined modulo f_s = 1, so the cell at
-             alpha = -1 of the Nyquist strip is the alpha = 0 (PSD) term).
+  off(k)     = bins with |(q + k_c N / Np) wrapped to [-N/2, N/2)| >= N/256, i.e. alpha at least 1/256 away
+             from 0 modulo 1 (a discrete-time signal's cycle frequencies are defined modulo f_s = 1, so the cell
+             at alpha = -1 of the Nyquist strip is the alpha = 0 (PSD) term). The guard is that wide because cells
+             a few bins from alpha = 0 sit tens of times above the strip's median for signals with power in the
+             strip (QPSK at 5 dB, N = 2^15: 37x at 2 bins, 44x at 8 bins), which an 8/N guard would count as
+             cyclic features; 1/256 stays below every cycle frequency of the test signals (symbol rates >= 1/16,
+             carriers >= 0.02).
   label_k    = 1 if max_{off} |S|^2 > T mean_{off} |S|^2 with T = 6.2^2 / 2 (about 1e-3 false alarms per
              2^18 bins of complex Gaussian noise, whose |S|^2 is exponentially distributed).
 MLP (BF16 operands, FP32 accumulation on the GPU; FP64 here, optionally with the same bf16 rounding of each
@@ -32,8 +36,8 @@ from . import scd_oracle as O
 
 B_F = 16
 N_C = 1024
-GUARD = 2
-ALPHA_GUARD = 8
+GUARD = 4
+ALPHA_GUARD_DIV = 256
 T_LABEL = 6.2 ** 2 / 2.0
 
 
@@ -80,7 +84,7 @@ def labels_from_scd(S):
     ratio = np.zeros(Np)
     for k in range(Np):
         kc = _signed(k, Np)
-        off = np.abs(_signed((q + kc * (N // Np)) % N, N)) >= ALPHA_GUARD
+        off = np.abs(_signed((q + kc * (N // Np)) % N, N)) >= N // ALPHA_GUARD_DIV
         p = np.abs(S[k, off]) ** 2
         ratio[k] = p.max() / p.mean()
         lab[k] = 1.0 if ratio[k] > T_LABEL else 0.0

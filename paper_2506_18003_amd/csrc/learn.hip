@@ -4,9 +4,9 @@
 // Features of a signal (2 Np floats): from the SSCA S_b of B_F = 16 segments of N_C = 1024 samples,
 //   A_k[q]  = sum_b |S_b[k][q]|^2 (averaged cyclic periodogram of strip k),
 //   PSD_k   = 0.5 log(A_k[q0(k)] + 1e-30) centred over k, q0(k) = (-k_c N_C / Np) mod N_C (alpha = 0 bin),
-//   ACP_k   = log(max / mean of A_k over the bins farther than 2 (circularly) from q0(k)).
+//   ACP_k   = log(max / mean of A_k over the bins farther than 4 (circularly) from q0(k)).
 // Labels from a full SSCA S [Np][N]: strip k is active if max |S|^2 exceeds T = 6.2^2/2 times the mean |S|^2
-// over the bins whose cycle frequency is at least 8/N away from 0 modulo 1.
+// over the bins whose cycle frequency is at least 1/256 away from 0 modulo 1.
 // MLP: 2 Np -> 256 -> 256 -> Np, ReLU, ReLU, sigmoid; parameters packed as [W1 b1 W2 b2 W3 b3] (FP32 master,
 // row-major W[out][in]); every GEMM rounds both operands to bf16 and accumulates in FP32 on
 // v_mfma_f32_32x32x16_bf16.
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void acp_features_kernel(const float2* __restr
     }
     if (q == q0) a0 = a;
     const int d = abs(signed_idx((q - q0) & (kNC - 1), kNC));
-    if (d > 2) {
+    if (d > 4) {
       sum += a;
       mx = fmaxf(mx, a);
       ++cnt;
@@ -103,10 +103,11 @@ __global__ __launch_bounds__(256) void labels_kernel(const float2* __restrict__ 
   const float2* row = S + (static_cast<int64_t>(sig) * Np + k) * N;
   const int n = static_cast<int>(N);
   const int shift = signed_idx(k, Np) * (n / Np);
+  const int guard = n / 256;
   float sum = 0.f, mx = 0.f;
   for (int q = tid; q < n; q += 256) {
     const int d = abs(signed_idx((q + shift) & (n - 1), n));
-    if (d >= 8) {
+    if (d >= guard) {
       const float2 v = row[q];
       const float p = fmaf(v.x, v.x, v.y * v.y);
       sum += p;
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void labels_kernel(const float2* __restrict__ 
   const float tot = block_sum(sum, red);
   const float m = block_max(mx, red);
   if (tid == 0) {
-    const float r = m / (tot / static_cast<float>(n - 15));
+    const float r = m / (tot / static_cast<float>(n - (2 * guard - 1)));
     if (ratio) ratio[sig * Np + k] = r;
     labels[sig * Np + k] = (r > kLabelT) ? 1.f : 0.f;
   }

@@ -30,6 +30,11 @@ def rng_for(config: int, index: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * config + index))
 
 
+def rng_keyed(*keys: int) -> np.random.Generator:
+    """Generator for an arbitrary tuple of integer keys (no overlap between different tuples)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, *keys])))
+
+
 def _symbols_to_samples(sym: np.ndarray, sps: int, n: int, rng: np.random.Generator) -> np.ndarray:
     """Rectangular pulse shaping with a random timing offset in [0, sps)."""
     off = int(rng.integers(0, sps))

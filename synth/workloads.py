@@ -48,14 +48,29 @@ def cfg3(n: int = 1 << 20):
     return dict(x=x, ssca=dict(N=n, Np=64, win=sg.hamming(64)))
 
 
-def cfg4_signal(i: int, n: int = 1 << 18, split: int = 4):
-    """Signal i of the selector data set; ``split`` keeps train/validation/test seeds disjoint."""
-    rng = sg.rng_for(4 + 10 * split, i)
+SPLITS = {"train": 0, "val": 1, "test": 2}
+
+
+def cfg4_signal(i: int, n: int = 1 << 18, split: str = "train"):
+    """Signal i of a selector data set split ("train", "val", "test"); the splits' seeds never overlap."""
+    rng = sg.rng_keyed(4, SPLITS[split], i)
     kind = sg.MODULATIONS[int(rng.integers(0, len(sg.MODULATIONS)))]
     fc = float(rng.uniform(0.02, 0.3))
     sps = int(rng.integers(4, 17))
     snr = float(rng.uniform(-10.0, 10.0))
     return kind, sg.generate(kind, n, rng, fc, sps, snr)
+
+
+def selector_signal(i: int, split: str = "train", emin: int = 14, emax: int = 20):
+    """Training signal for the Np = 64 / 128 selectors: length 2^e, e ~ U{emin..emax}, and the modulation,
+    carrier, rate and SNR ranges of the combined workload (SNR ~ U[-10, 15] dB)."""
+    rng = sg.rng_keyed(6, SPLITS[split], i)
+    e = int(rng.integers(emin, emax + 1))
+    kind = sg.MODULATIONS[int(rng.integers(0, len(sg.MODULATIONS)))]
+    fc = float(rng.uniform(0.02, 0.3))
+    sps = int(rng.integers(4, 17))
+    snr = float(rng.uniform(-10.0, 15.0))
+    return kind, sg.generate(kind, 1 << e, rng, fc, sps, snr)
 
 
 def cfg5_signal(i: int):

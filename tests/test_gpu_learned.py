@@ -1,4 +1,6 @@
 """GPU parity of the learned strip selector against its FP64 reference (oracle/learn_ref.py)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -162,3 +164,66 @@ def test_learned_ssca_fallback_forced(dev):
     out, mask, fb = SEL.ssca_learned(x, sel)
     assert fb and int(mask.sum()) == Np
     assert torch.equal(out, scd.ssca(x, Np))
+
+
+MODELS = os.path.join(os.path.dirname(SEL.__file__), "models")
+
+
+def _model(Np, dev):
+    path = f"{MODELS}/selector_np{Np}.npz"
+    if not os.path.exists(path):
+        pytest.skip(f"no trained model for Np={Np}")
+    return SEL.Selector.load(path, dev)
+
+
+def test_trained_selector_recall_on_held_out_cfg4(dev):
+    """Held-out signals of the Np = 256, N = 2^18 selector workload (test-split seeds): strip recall >= 0.99
+    with the committed model and its calibrated threshold (fallback counted as full recall), and fewer strips
+    computed than the full SSCA, which is what the network gains over the method without it."""
+    from synth import workloads as W
+    sel = _model(256, dev)
+    Np, N, count = 256, 1 << 18, 96
+    tp = pos = work = 0
+    for i in range(0, count, 8):
+        xs = np.stack([W.cfg4_signal(j, N, "test")[1] for j in range(i, i + 8)]).astype(np.complex64)
+        x = torch.from_numpy(xs).to(dev)
+        lab, _ = SEL.strip_labels(scd.ssca(x, Np))
+        feat = SEL.features(x, Np)
+        s = sel.scores(feat).cpu().numpy()
+        lab = lab.cpu().numpy() > 0.5
+        conf = np.min(np.maximum(s, 1 - s), axis=1)
+        chosen = s >= sel.theta
+        chosen[conf < sel.conf_min] = True
+        tp += (chosen & lab).sum()
+        pos += lab.sum()
+        work += chosen.sum()
+    recall = tp / max(1, pos)
+    assert recall >= 0.99, recall
+    assert work < count * Np
+
+
+def test_combined_workload_split_bf16_learned(dev):
+    """The combined form on signals of the cfg-5 recipe (uneven lengths 2^14..2^20, Np = 64): split-BF16 +
+    learned selection + fallback. Every selected strip equals the full split-BF16 SSCA's, the recall over the
+    labels of the full FP32 SSCA is >= 0.99, and the split-BF16 strips stay within 1e-3 of the FP64 oracle."""
+    from synth import workloads as W
+    sel = _model(64, dev)
+    tp = pos = 0
+    for i in range(0, 16, 2):  # the even indices of the workload use Np = 64
+        c = W.cfg5_signal(i)
+        x = torch.from_numpy(c["x"].astype(np.complex64)).to(dev)
+        out, mask, fb = SEL.ssca_learned(x, sel, precision="split_bf16")
+        full32 = scd.ssca(x, 64)
+        full16 = scd.ssca(x, 64, precision="split_bf16")
+        m = mask.cpu().numpy().astype(bool)
+        lab = SEL.strip_labels(full32)[0].cpu().numpy()[0] > 0.5
+        tp += (m & lab).sum()
+        pos += lab.sum()
+        k = torch.from_numpy(np.nonzero(m)[0]).to(dev)
+        assert torch.equal(out[k], full16[k]), i
+        if m.any():
+            kk = int(np.nonzero(m)[0][0])
+            ref = O.ssca_strip(f64(c["x"]), 64, sg.hamming(64).astype(np.float32).astype(np.float64), kk)
+            g = out[kk].cpu().numpy()
+            assert np.abs(g - ref).max() <= 1e-3 * np.abs(ref).max(), i
+    assert tp / max(1, pos) >= 0.99

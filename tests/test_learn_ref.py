@@ -66,7 +66,7 @@ def test_bf16_round_against_torch_and_ties():
 
 
 def test_labels_pure_noise_all_zero_and_bpsk_has_active_strips():
-    N, Np = 4096, 16
+    N, Np = 8192, 16
     w = sg.hamming(Np)
     lab, ratio = LR.labels_from_scd(O.ssca(sg.noise(N, sg.rng_for(70, 0)), Np, w))
     assert lab.sum() == 0 and ratio.max() < LR.T_LABEL
