@@ -11,6 +11,9 @@ event-timed duration against the 8 TB/s HBM peak. `cpu_baseline` times the FP64 
 against it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline]
+       python bench.py --write-traffic FETCH_CSV WRITE_CSV   (no GPU: summarise two rocprofv3 --pmc runs of
+       `bench.py --copy-calib --forms fp32`, one with FETCH_SIZE and one with WRITE_SIZE, into the committed
+       per-launch HBM traffic of the SSCA kernels)
 """
 from __future__ import annotations
 
@@ -52,7 +55,50 @@ def measured_traffic(kernel: str, digest: str):
     return k.get("bytes_per_launch")
 
 
+CALIB_BYTES = 256 << 20          # the --copy-calib kernel reads and writes this many bytes
+TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32", "ssca_pass2": "ssca_pass2_fp32"}
+
+
+def write_traffic(fetch_csv: str, write_csv: str) -> dict:
+    """Per-launch HBM bytes of each SSCA kernel from FETCH_SIZE / WRITE_SIZE counter CSVs (KiB per dispatch),
+    each counter scaled by the factor that maps its reading of the calibration kernel to the known size."""
+    import csv
+
+    def per_kernel(path):
+        acc = {}
+        for row in csv.DictReader(open(path)):
+            acc.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]) * 1024.0)
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    out = {"source_digest": source_digest(), "calibration": {}, "kernels": {}}
+    readings = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        pk = per_kernel(path)
+        calib = [v for k, v in pk.items() if "MulFunctor" in k]
+        if len(calib) != 1:
+            raise SystemExit(f"{path}: expected one calibration kernel reading")
+        factor = CALIB_BYTES / calib[0]
+        out["calibration"][counter] = {"raw_bytes": calib[0], "known_bytes": CALIB_BYTES, "factor": factor}
+        for name, pat in TRAFFIC_KERNELS.items():
+            hits = [v for k, v in pk.items() if pat in k]
+            if len(hits) != 1:
+                raise SystemExit(f"{path}: expected one {pat} kernel, found {len(hits)}")
+            readings.setdefault(name, {})[counter] = hits[0] * factor
+    for name, r in readings.items():
+        out["kernels"][name] = {"fetch_bytes": round(r["FETCH_SIZE"]), "write_bytes": round(r["WRITE_SIZE"]),
+                                "bytes_per_launch": round(r["FETCH_SIZE"] + r["WRITE_SIZE"])}
+    path = os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+    return out
+
+
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--write-traffic":
+        write_traffic(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -60,7 +106,7 @@ def main():
     ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
-                    help="also run one plain 256 MiB device-to-device copy (calibrates HBM byte counters)")
+                    help="also run one 256 MiB read + 256 MiB write elementwise kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the SSCA strips would shard over GPUs by channel, but this "
@@ -85,11 +131,11 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     if args.copy_calib:
-        src = torch.empty(32 << 20, dtype=torch.complex64, device=dev)
+        # A plain streaming kernel of known traffic (256 MiB read, 256 MiB written) to scale HBM byte counters.
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        src.zero_()
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
