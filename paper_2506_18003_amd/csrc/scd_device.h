@@ -153,12 +153,64 @@ __device__ __forceinline__ void dft16(float2* a) {
   }
 }
 
+constexpr float kC32a = 0.98078528040323044913f;  // cos(pi/16)
+constexpr float kS32a = 0.19509032201612826785f;  // sin(pi/16)
+constexpr float kC32b = 0.83146961230254523708f;  // cos(3 pi/16)
+constexpr float kS32b = 0.55557023301960222474f;  // sin(3 pi/16)
+
+// a * omega_32^E for a compile-time exponent E.
+template <int E>
+__device__ __forceinline__ float2 rot32(float2 a) {
+  constexpr int e = ((E % 32) + 32) % 32;
+  if constexpr (e % 2 == 0) {
+    return rot16<e / 2>(a);
+  } else {
+    // omega_32^e = cos(pi e/16) - i sin(pi e/16); first-quadrant angle pi r/16 (r odd), then (-i)^q
+    constexpr int q = e / 8, r = e % 8;
+    constexpr float c0 = r == 1 ? kC32a : r == 3 ? kC32b : r == 5 ? kS32b : kS32a;
+    constexpr float s0 = r == 1 ? kS32a : r == 3 ? kS32b : r == 5 ? kC32b : kC32a;
+    float2 b = make_float2(fmaf(a.x, c0, a.y * s0), fmaf(a.y, c0, -a.x * s0));
+    if constexpr (q == 0) return b;
+    else if constexpr (q == 1) return mul_mi(b);
+    else if constexpr (q == 2) return make_float2(-b.x, -b.y);
+    else return make_float2(-b.y, b.x);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void rot32_odd_half(float2* o) {
+  if constexpr (K < 16) {
+    o[K] = rot32<K>(o[K]);
+    rot32_odd_half<K + 1>(o);
+  }
+}
+
+// 32-point DFT = 2 x 16: X[k] = E[k] + omega_32^k O[k], X[k + 16] = E[k] - omega_32^k O[k], with E and O the
+// 16-point DFTs of the even and odd samples.
+__device__ __forceinline__ void dft32(float2* a) {
+  float2 e[16], o[16];
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    e[n] = a[2 * n];
+    o[n] = a[2 * n + 1];
+  }
+  dft16(e);
+  dft16(o);
+  rot32_odd_half<1>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    a[k] = cadd(e[k], o[k]);
+    a[k + 16] = csub(e[k], o[k]);
+  }
+}
+
 template <int R>
 __device__ __forceinline__ void dft(float2* a) {
   if constexpr (R == 2) dft2(a);
   else if constexpr (R == 4) dft4(a);
   else if constexpr (R == 8) dft8(a);
   else if constexpr (R == 16) dft16(a);
+  else if constexpr (R == 32) dft32(a);
   else static_assert(R == 1, "unsupported radix");
 }
 
@@ -190,8 +242,9 @@ struct NoStore {};
 // omega_{NS R}^{i (j mod NS)}, takes an R-point DFT and writes output i to (j/NS)*NS*R + (j mod NS) + i*NS.
 // BFAST selects the enumeration of butterflies over threads: sequence index fastest (true) or j fastest.
 // All threads read their inputs before the barrier and write after it, so the stage runs in place.
-template <int L, int NB, int NT, int NS, bool BFAST, class Lay, class LoadF, class StoreF>
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, class LoadF, class StoreF>
 __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
+  static_assert(TWN >= L, "the twiddle table must hold at least L roots");
   constexpr int R = StageRadix<L, NS>::value;
   constexpr int NBF = NB * (L / R);
   constexpr int PER = (NBF + NT - 1) / NT;
@@ -215,7 +268,7 @@ __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, in
       }
       if constexpr (NS > 1) {
 #pragma unroll
-        for (int i = 1; i < R; ++i) v[p][i] = cmul(v[p][i], tw[(i * k * (1024 / (NS * R))) & 1023]);
+        for (int i = 1; i < R; ++i) v[p][i] = cmul(v[p][i], tw[(i * k * (TWN / (NS * R))) & (TWN - 1)]);
       }
       dft<R>(v[p]);
     }
@@ -239,12 +292,12 @@ __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, in
   if constexpr (!STORE_EXT) __syncthreads();
 }
 
-template <int L, int NB, int NT, int NS, bool BFAST, class Lay, class LoadF, class StoreF>
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, class LoadF, class StoreF>
 __device__ __forceinline__ void stockham_from(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   if constexpr (NS < L) {
-    stockham_stage<L, NB, NT, NS, BFAST, Lay>(buf, tw, tid, ld, st);
+    stockham_stage<L, NB, NT, NS, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
     constexpr int R = StageRadix<L, NS>::value;
-    stockham_from<L, NB, NT, NS * R, BFAST, Lay>(buf, tw, tid, ld, st);
+    stockham_from<L, NB, NT, NS * R, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
   }
 }
 
@@ -291,19 +344,20 @@ struct FirstStage {
   }
 };
 
-template <int L, int NB, int NT, bool BFAST, class Lay, class StoreF>
+template <int L, int NB, int NT, bool BFAST, class Lay, int TWN = 1024, class StoreF>
 __device__ __forceinline__ void stockham_rest(float2* buf, const float2* tw, int tid, StoreF& st) {
   NoLoad ld;
-  stockham_from<L, NB, NT, StageRadix<L, 1>::value, BFAST, Lay>(buf, tw, tid, ld, st);
+  stockham_from<L, NB, NT, StageRadix<L, 1>::value, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
 }
 
 // Forward DFT of NB length-L sequences (L a power of two, 2 <= L <= 1024), natural order in and out.
 // Requires a barrier before the call if the data were just written to LDS by other threads. On return the
 // outputs are either in LDS (followed by a barrier) or were handed to `st(b, m, value)`.
-template <int L, int NB, int NT, bool BFAST, class Lay, class LoadF, class StoreF>
+// `tw` holds omega_TWN^e for e < TWN (TWN >= L, a power of two).
+template <int L, int NB, int NT, bool BFAST, class Lay, int TWN = 1024, class LoadF, class StoreF>
 __device__ __forceinline__ void lds_fft(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   static_assert(L >= 2 && L <= 1024 && (L & (L - 1)) == 0, "length must be a power of two in [2, 1024]");
-  stockham_from<L, NB, NT, 1, BFAST, Lay>(buf, tw, tid, ld, st);
+  stockham_from<L, NB, NT, 1, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
 }
 
 }  // namespace scd

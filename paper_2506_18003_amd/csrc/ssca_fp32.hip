@@ -259,6 +259,58 @@ __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __re
   p2_stage<M2, 1>(src, dst, buf, tw, tid);
 }
 
+// Stage 2 for M2 = 1024 as 32 x 32, with m2 = j + 32 i and m2' = i' + 32 j':
+//   X[i' + 32 j'] = sum_j omega_32^{j j'} omega_1024^{j i'} sum_i omega_32^{i i'} x[j + 32 i].
+// Thread (row pair rp, j) loads x[j + 32 i] (i < 32) of its two rows straight from HBM, takes both 32-point
+// DFTs over i in registers and applies omega_1024^{j i'}. The exchange runs in two halves of i' (16 each,
+// 66 KB of LDS); thread (row, i') then takes the 32-point DFT over j and stores X[i' + 32 j'] of its row.
+// Two workgroups share a CU, so one workgroup's HBM traffic overlaps another's arithmetic.
+constexpr int kP2XStride = 32 * 16 + 16;  // LDS stride of one i': 32 j x 16 rows, plus 16 float2 of padding
+
+__global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const float2* __restrict__ T,
+                                                                      const float2* __restrict__ tabs,
+                                                                      float2* __restrict__ out, int N, int64_t tbs,
+                                                                      int64_t obs, const ChanSel* __restrict__ sel) {
+  __shared__ float2 buf[16 * kP2XStride];
+  __shared__ float2 tw[1024];
+  const int tid = threadIdx.x;
+  const int mb = blockIdx.x;  // block of 16 consecutive m1'
+  const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
+  for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
+  const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (1024 * 16);
+  float2* dst = out + blockIdx.z * obs + static_cast<int64_t>(k) * N + mb * 16;
+  const int rp = tid & 7, j = tid >> 3;
+  float2 a[32], b[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) ld2_nt(src + (j + 32 * i) * 16 + 2 * rp, a[i], b[i]);
+  dft32(a);
+  dft32(b);
+  __syncthreads();
+#pragma unroll
+  for (int ip = 1; ip < 32; ++ip) {
+    const float2 w = tw[(j * ip) & 1023];
+    a[ip] = cmul(a[ip], w);
+    b[ip] = cmul(b[ip], w);
+  }
+  const int row = tid & 15, ipl = tid >> 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      *reinterpret_cast<float4*>(buf + q * kP2XStride + j * 16 + 2 * rp) =
+          make_float4(a[16 * h + q].x, a[16 * h + q].y, b[16 * h + q].x, b[16 * h + q].y);
+    __syncthreads();
+    float2 v[32];
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) v[jj] = buf[ipl * kP2XStride + jj * 16 + row];
+    dft32(v);
+    const int ip = 16 * h + ipl;
+#pragma unroll
+    for (int jp = 0; jp < 32; ++jp) st1_nt(dst + static_cast<int64_t>(ip + 32 * jp) * kM1 + row, v[jp]);
+  }
+}
+
 template <int NP>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* hc,
                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
@@ -284,7 +336,10 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int ba
                  const SelArg& sel, hipStream_t s) {
   if (sel.nch <= 0) return hipSuccess;
   dim3 grid(kM1 / 16, sel.nch, batch);
-  hipLaunchKernelGGL(ssca_pass2_fp32<M2>, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
+  if constexpr (M2 == 1024)
+    hipLaunchKernelGGL(ssca_pass2_fp32_32x32, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
+  else
+    hipLaunchKernelGGL(ssca_pass2_fp32<M2>, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
   return hipGetLastError();
 }
 
