@@ -49,15 +49,20 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 
 // Stage 1. The flattened block index is mapped so that each of the 8 XCDs (which receive blocks round-robin)
 // walks a contiguous range of m2: the frames of neighbouring m2 overlap in all but one sample, so an XCD's
-// share of x stays in its L2. Thread t owns frames m1 = t + 256 f (f < 4). Frame samples are staged through
-// two LDS buffers (JS samples of 256 frames each), the next sub-chunk's loads in flight while the current one
-// is folded. Each thread folds its frame with the subset's complex window (read through the scalar cache),
-// takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does not divide M2, by the per-frame
-// down-conversion factor), keeping the 16 channel values in registers. The M1 = 1024-point DFT over
-// m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle omega_1024^{t r}, and a 256-point DFT over t
-// in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its last radix stage stores to HBM, multiplying by
-// the rotation factor omega_N^{m2 m1'} (and by the down-conversion factor omega_Np^{(k m2) mod Np}, which
-// does not depend on m1 when Np divides M2), built per butterfly as a base times a per-block step table.
+// share of x stays in its L2. Thread t owns frames m1 = t + 256 f (f < 4).
+//
+// Fold: for each group f of 256 frames, lane (frame i = 16 r + tid / 16, residue j0 = tid % 16) forms
+// u[j0] = sum_{j1 < Np/16} hc[j0 + 16 j1] x[n - d + j0 + 16 j1] over rounds r < 16. A wave's loads cover
+// 4 frames x 16 consecutive samples (whole 128-byte lines, straight from L2, with loads for the next rounds
+// kept in flight in a register ring), and only the 16 folded values per frame pass through LDS, where thread t
+// picks up frame t's row. It then takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does not
+// divide M2, by the per-frame down-conversion factor), keeping the 16 channel values in registers.
+//
+// The M1 = 1024-point DFT over m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle
+// omega_1024^{t r}, and a 256-point DFT over t in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its
+// last radix stage stores to HBM, multiplying by the rotation factor omega_N^{m2 m1'} (and by the
+// down-conversion factor omega_Np^{(k m2) mod Np}, which does not depend on m1 when Np divides M2), built per
+// butterfly as a base times a per-block step table.
 template <int NP, bool PHASE_BY_M2, bool SEL>
 __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* __restrict__ x, int N, int M2,
                                                                 int m2shift, const float2* __restrict__ hcg,
@@ -66,11 +71,12 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
                                                                 const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
   constexpr int D = NP / 2 - 1;
-  constexpr int JS = NP < 16 ? NP : 16;  // samples per sub-chunk
-  constexpr int NSUB = NP / JS;
-  constexpr int kStage = kP1Threads * (JS + 1);
-  static_assert(2 * kStage >= kXchgFloats, "exchange must fit in the staging buffers");
-  __shared__ float2 buf[2 * kStage];
+  constexpr int NT = NP / 16;           // taps per residue
+  constexpr int PF = 16 / NT;           // rounds of loads in flight
+  constexpr int kURow = 17;             // LDS row of one frame's folded values (16 + 1 padding)
+  constexpr int kUBuf = kP1Threads * kURow;
+  static_assert(2 * kUBuf <= kXchgFloats, "fold buffers must fit in the exchange buffer");
+  __shared__ float2 buf[kXchgFloats];
   __shared__ float2 tw[1024];
   __shared__ float2 stp[16];
   __shared__ float2 rt[NP];
@@ -95,44 +101,37 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
     stp[tid] = rot_factor(rlo, tw_g, 64 * m2 * tid, hishift);
   }
 
-  // Sub-chunk s covers frames m1 = 256 (s / NSUB) + i, i < 256, samples JS * (s % NSUB) + jj, jj < JS.
-  float2 pf[JS];
-  auto issue = [&](int s) {
-    const int jbase = (256 * (s / NSUB)) * M2 + m2 - D + (s % NSUB) * JS;
+  const int j0 = tid & 15, fi = tid >> 4;
+  float2 hl[NT];
 #pragma unroll
-    for (int q = 0; q < JS; ++q) {
-      const int e = tid + kP1Threads * q;
-      pf[q] = load_c64(xr, jbase + (e / JS) * M2 + (e % JS));
-    }
-  };
-  auto stash = [&](int s) {
-    float2* b = buf + (s & 1) * kStage;
+  for (int j1 = 0; j1 < NT; ++j1) hl[j1] = hc[j0 + 16 * j1];
+  // Round g = 16 f + r folds frames m1 = 16 g + fi; its NT samples sit at x[base + 16 j1].
+  const int base0 = fi * M2 + m2 - D + j0;
+  float2 ring[PF][NT];
+  auto issue = [&](int g) {
 #pragma unroll
-    for (int q = 0; q < JS; ++q) {
-      const int e = tid + kP1Threads * q;
-      b[(e / JS) * (JS + 1) + (e % JS)] = pf[q];
-    }
+    for (int j1 = 0; j1 < NT; ++j1) ring[g % PF][j1] = load_c64(xr, base0 + 16 * g * M2 + 16 * j1);
   };
-  issue(0);
-  stash(0);
-  if (NSUB * 4 > 1) issue(1);
+#pragma unroll
+  for (int g = 0; g < PF; ++g) issue(g);
 
   float2 col[4][16];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
+    float2* ub = buf + (f & 1) * kUBuf;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int g = 16 * f + r;
+      float2 acc = cmul(hl[0], ring[g % PF][0]);
+#pragma unroll
+      for (int j1 = 1; j1 < NT; ++j1) acc = cfma(acc, hl[j1], ring[g % PF][j1]);
+      if (g + PF < 64) issue(g + PF);
+      ub[(16 * r + fi) * kURow + j0] = acc;
+    }
+    __syncthreads();
     float2 u[16];
 #pragma unroll
-    for (int j0 = 0; j0 < 16; ++j0) u[j0] = make_float2(0.f, 0.f);
-#pragma unroll 1
-    for (int sub = 0; sub < NSUB; ++sub) {
-      const int s = f * NSUB + sub;
-      __syncthreads();
-      const float2* b = buf + (s & 1) * kStage + tid * (JS + 1);
-#pragma unroll
-      for (int jj = 0; jj < JS; ++jj) u[jj & 15] = cfma(u[jj & 15], hc[sub * JS + jj], b[jj]);
-      if (s + 1 < 4 * NSUB) stash(s + 1);
-      if (s + 2 < 4 * NSUB) issue(s + 2);
-    }
+    for (int j = 0; j < 16; ++j) u[j] = ub[tid * kURow + j];
     dft16(u);
     const int n = (tid + 256 * f) * M2 + m2;
     const float2 xn = load_c64(xr, n);
