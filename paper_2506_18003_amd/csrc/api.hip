@@ -556,7 +556,7 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
   e = hipMemcpyAsync(dsel, &hsel, sizeof(hsel), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "selection upload");
-  const scd::SelArg sel{dsel, hsel.nsub, hsel.nch};
+  const scd::SelArg sel{dsel, hsel.nsub, hsel.npair, hsel.nch};
   scd_opts so{};
   if (opts) so = *opts;
   so.batch = 1;

@@ -20,13 +20,16 @@ constexpr int SCD_PREC_BF16 = 3;
 constexpr int SCD_PREC_FP16 = 4;
 constexpr int kMfmaPad = 256;  // zero samples on each side of the 16-bit copies of x
 
-// Which strips an SSCA launch computes (passed by value as a kernel argument). Stage 1 runs the channel
-// subsets sub[0..nsub) and stores strip k only if bit k of keep is set; stage 2 runs strips ch[0..nch).
+// Which strips an SSCA launch computes (read by the kernels from device memory). Stage 1 runs the channel
+// subsets sub[0..nsub) (subset c holds the strips k = c (mod Np/16)), or, in its paired form, the subset pairs
+// pair[0..npair) (pair p holds subsets p and p + Np/32), and stores strip k only if bit k of keep is set;
+// stage 2 runs strips ch[0..nch).
 struct ChanSel {
   unsigned keep[8];
   unsigned char sub[16];
+  unsigned char pair[8];
   unsigned char ch[256];
-  int nsub, nch;
+  int nsub, npair, nch;
 };
 // Every strip of an Np-channel SSCA.
 ChanSel chansel_all(int Np);
@@ -36,9 +39,9 @@ ChanSel chansel_from_mask(int Np, const unsigned char* mask);
 // through the scalar cache; dev == nullptr means every strip (sub[i] = i, ch[k] = k, all kept).
 struct SelArg {
   const ChanSel* dev;
-  int nsub, nch;
+  int nsub, npair, nch;
 };
-inline SelArg selarg_all(int Np) { return SelArg{nullptr, Np / 16, Np}; }
+inline SelArg selarg_all(int Np) { return SelArg{nullptr, Np / 16, Np / 32, Np}; }
 
 hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 

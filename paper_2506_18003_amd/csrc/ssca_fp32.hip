@@ -49,53 +49,67 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 
 // Stage 1. The flattened block index is mapped so that each of the 8 XCDs (which receive blocks round-robin)
 // walks a contiguous range of m2: the frames of neighbouring m2 overlap in all but one sample, so an XCD's
-// share of x stays in its L2. Thread t owns frames m1 = t + 256 f (f < 4).
+// share of x stays in its L2. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
+// a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2, with 256 threads per subset;
+// thread t of a subset owns frames m1 = t + 256 f (f < 4).
 //
-// Fold: for each group f of 256 frames, lane (frame i = 16 r + tid / 16, residue j0 = tid % 16) forms
-// u[j0] = sum_{j1 < Np/16} hc[j0 + 16 j1] x[n - d + j0 + 16 j1] over rounds r < 16. A wave's loads cover
-// 4 frames x 16 consecutive samples (whole 128-byte lines, straight from L2, with loads for the next rounds
-// kept in flight in a register ring), and only the 16 folded values per frame pass through LDS, where thread t
-// picks up frame t's row. It then takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does not
-// divide M2, by the per-frame down-conversion factor), keeping the 16 channel values in registers.
+// Fold: for each group f of 256 frames, lane (frame i, residue j0 = tid % 16) forms
+//   A = sum_{j1 < Np/16} hc[j0 + 16 j1] x[n - d + j0 + 16 j1]
+// over the rounds that cover the group. A wave's loads cover 4 frames x 16 consecutive samples (whole
+// 128-byte lines, straight from L2, with loads for the next rounds kept in flight in a register ring), and
+// only 16 folded values per frame pass through LDS, where thread t picks up frame t's row. In a pair the
+// same loads serve both subsets: with j = j0 + 32 m + 16 e, the 32-channel subset c (strips c mod Np/32) is the
+// 32-point DFT of u[j0 + 16 e] = sum_m hc[j0 + 32 m + 16 e] x[...]; its even outputs are the 16-point DFT of
+// u[j0] + u[j0 + 16] (subset c) and its odd outputs that of (u[j0] - u[j0 + 16]) omega_32^{j0}
+// (subset c + Np/32). Each thread then takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does
+// not divide M2, by the per-frame down-conversion factor), keeping the 16 channel values in registers.
 //
 // The M1 = 1024-point DFT over m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle
 // omega_1024^{t r}, and a 256-point DFT over t in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its
 // last radix stage stores to HBM, multiplying by the rotation factor omega_N^{m2 m1'} (and by the
 // down-conversion factor omega_Np^{(k m2) mod Np}, which does not depend on m1 when Np divides M2), built per
 // butterfly as a base times a per-block step table.
-template <int NP, bool PHASE_BY_M2, bool SEL>
-__global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* __restrict__ x, int N, int M2,
-                                                                int m2shift, const float2* __restrict__ hcg,
-                                                                const float2* __restrict__ tabs,
-                                                                float2* __restrict__ T, int64_t xbs, int64_t tbs,
-                                                                const ChanSel* __restrict__ sel) {
+template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR>
+__global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) void ssca_pass1_fp32(
+    const float2* __restrict__ x, int N, int M2, int m2shift, const float2* __restrict__ hcg,
+    const float2* __restrict__ tabs, float2* __restrict__ T, int64_t xbs, int64_t tbs,
+    const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
   constexpr int D = NP / 2 - 1;
-  constexpr int NT = NP / 16;           // taps per residue
-  constexpr int PF = 16 / NT;           // rounds of loads in flight
+  constexpr int NH = PAIR ? 2 : 1;      // channel subsets per workgroup
+  constexpr int NTH = NH * kP1Threads;
+  constexpr int NT = NP / 16;           // taps per lane and round
+  constexpr int FPR = NTH / 16;         // frames per round
+  constexpr int RPG = 256 / FPR;        // rounds per group of 256 frames
+  constexpr int NR = 4 * RPG;
+  constexpr int PF = 16 / NT < NR ? 16 / NT : NR;  // rounds of loads in flight
   constexpr int kURow = 17;             // LDS row of one frame's folded values (16 + 1 padding)
   constexpr int kUBuf = kP1Threads * kURow;
   static_assert(2 * kUBuf <= kXchgFloats, "fold buffers must fit in the exchange buffer");
-  __shared__ float2 buf[kXchgFloats];
+  static_assert(!PAIR || NT % 2 == 0, "a subset pair needs Np >= 32");
+  __shared__ float2 buf[NH * kXchgFloats];
   __shared__ float2 tw[1024];
   __shared__ float2 stp[16];
   __shared__ float2 rt[NP];
 
   const int tid = threadIdx.x;
+  const int half = PAIR ? (tid >> 8) : 0;
+  const int t = tid & (kP1Threads - 1);
   const int nblk = gridDim.x;
   int lin = blockIdx.x;
   if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
-  const int c = SEL ? sel->sub[lin >> m2shift] : (lin >> m2shift);
+  const int cg = SEL ? (PAIR ? sel->pair[lin >> m2shift] : sel->sub[lin >> m2shift]) : (lin >> m2shift);
+  const int c = cg + half * (S / 2);  // this thread's subset
   const int m2 = lin & (M2 - 1);
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
   const float2* rlo = tabs + kTabRotLo;
-  const float2* hc = hcg + c * NP;
+  const float2* hc = hcg + cg * NP;
   const auto xr = make_rsrc(x, N * 8);
   const int hishift = 10 - m2shift;
 
-  for (int i = tid; i < 1024; i += kP1Threads) tw[i] = tabs[kTabTw1024 + i];
-  for (int i = tid; i < NP; i += kP1Threads) rt[i] = tabs[kTabRoots + i];
+  for (int i = tid; i < 1024; i += NTH) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < NP; i += NTH) rt[i] = tabs[kTabRoots + i];
   if (tid < 16) {
     const float2* tw_g = tabs + kTabTw1024;
     stp[tid] = rot_factor(rlo, tw_g, 64 * m2 * tid, hishift);
@@ -105,12 +119,13 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
   float2 hl[NT];
 #pragma unroll
   for (int j1 = 0; j1 < NT; ++j1) hl[j1] = hc[j0 + 16 * j1];
-  // Round g = 16 f + r folds frames m1 = 16 g + fi; its NT samples sit at x[base + 16 j1].
+  const float2 w32 = tabs[kTabTw1024 + 32 * j0];  // omega_32^{j0}
+  // Round g folds frames m1 = FPR g + fi; its NT samples sit at x[base + 16 j1].
   const int base0 = fi * M2 + m2 - D + j0;
   float2 ring[PF][NT];
   auto issue = [&](int g) {
 #pragma unroll
-    for (int j1 = 0; j1 < NT; ++j1) ring[g % PF][j1] = load_c64(xr, base0 + 16 * g * M2 + 16 * j1);
+    for (int j1 = 0; j1 < NT; ++j1) ring[g % PF][j1] = load_c64(xr, base0 + FPR * g * M2 + 16 * j1);
   };
 #pragma unroll
   for (int g = 0; g < PF; ++g) issue(g);
@@ -118,22 +133,36 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
   float2 col[4][16];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    float2* ub = buf + (f & 1) * kUBuf;
+    float2* ub = buf + (f & 1) * NH * kUBuf;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int g = 16 * f + r;
-      float2 acc = cmul(hl[0], ring[g % PF][0]);
+    for (int r = 0; r < RPG; ++r) {
+      const int g = RPG * f + r;
+      const int row = (FPR * r + fi) * kURow + j0;
+      if constexpr (PAIR) {
+        float2 ea = cmul(hl[0], ring[g % PF][0]);
+        float2 eb = cmul(hl[1], ring[g % PF][1]);
 #pragma unroll
-      for (int j1 = 1; j1 < NT; ++j1) acc = cfma(acc, hl[j1], ring[g % PF][j1]);
-      if (g + PF < 64) issue(g + PF);
-      ub[(16 * r + fi) * kURow + j0] = acc;
+        for (int j1 = 2; j1 < NT; j1 += 2) {
+          ea = cfma(ea, hl[j1], ring[g % PF][j1]);
+          eb = cfma(eb, hl[j1 + 1], ring[g % PF][j1 + 1]);
+        }
+        if (g + PF < NR) issue(g + PF);
+        ub[row] = cadd(ea, eb);
+        ub[kUBuf + row] = cmul(csub(ea, eb), w32);
+      } else {
+        float2 acc = cmul(hl[0], ring[g % PF][0]);
+#pragma unroll
+        for (int j1 = 1; j1 < NT; ++j1) acc = cfma(acc, hl[j1], ring[g % PF][j1]);
+        if (g + PF < NR) issue(g + PF);
+        ub[row] = acc;
+      }
     }
     __syncthreads();
     float2 u[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) u[j] = ub[tid * kURow + j];
+    for (int j = 0; j < 16; ++j) u[j] = ub[half * kUBuf + t * kURow + j];
     dft16(u);
-    const int n = (tid + 256 * f) * M2 + m2;
+    const int n = (t + 256 * f) * M2 + m2;
     const float2 xn = load_c64(xr, n);
 #pragma unroll
     for (int kp = 0; kp < 16; ++kp) {
@@ -147,7 +176,7 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
   }
 
   // 4-point DFT over f and twiddle omega_1024^{t r}: col[r][k'] now holds residue r of channel k'.
-  const float2 t1 = tw[tid], t2 = tw[2 * tid], t3 = tw[3 * tid];
+  const float2 t1 = tw[t], t2 = tw[2 * t], t3 = tw[3 * t];
 #pragma unroll
   for (int kp = 0; kp < 16; ++kp) {
     float2 a[4] = {col[0][kp], col[1][kp], col[2][kp], col[3][kp]};
@@ -158,13 +187,14 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
     col[3][kp] = cmul(a[3], t3);
   }
 
+  float2* xb = buf + half * kXchgFloats;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) buf[(kk * 4 + r) * kSeqStride + tid + (tid >> 4)] = col[r][8 * h + kk];
+      for (int r = 0; r < 4; ++r) xb[(kk * 4 + r) * kSeqStride + t + (t >> 4)] = col[r][8 * h + kk];
     }
     __syncthreads();
     // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i.
@@ -178,7 +208,7 @@ __global__ __launch_bounds__(kP1Threads, 2) void ssca_pass1_fp32(const float2* _
         st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
     };
     NoLoad ld;
-    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
+    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>>(xb, tw, t, ld, st);
   }
 }
 
@@ -314,18 +344,21 @@ template <int NP>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* hc,
                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   constexpr int S = NP / 16;
-  if (sel.nsub <= 0) return hipSuccess;
+  constexpr bool PAIR = NP >= 32;  // subsets c and c + Np/32 share one workgroup
+  const int units = PAIR ? sel.npair : sel.nsub;
+  if (units <= 0) return hipSuccess;
   hipLaunchKernelGGL(ssca_hc_kernel, dim3((S * NP + 255) / 256), dim3(256), 0, s, win, tabs, hc, NP, S);
-  dim3 grid(M2 * sel.nsub, batch);
+  dim3 grid(M2 * units, batch);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3(kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T, xbs, tbs, sel.dev);
+    hipLaunchKernelGGL(kern, grid, dim3((PAIR ? 2 : 1) * kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T, xbs,
+                       tbs, sel.dev);
   };
   if (M2 % NP == 0) {
-    if (sel.dev) go(ssca_pass1_fp32<NP, true, true>);
-    else go(ssca_pass1_fp32<NP, true, false>);
+    if (sel.dev) go(ssca_pass1_fp32<NP, true, true, PAIR>);
+    else go(ssca_pass1_fp32<NP, true, false, PAIR>);
   } else {
-    if (sel.dev) go(ssca_pass1_fp32<NP, false, true>);
-    else go(ssca_pass1_fp32<NP, false, false>);
+    if (sel.dev) go(ssca_pass1_fp32<NP, false, true, PAIR>);
+    else go(ssca_pass1_fp32<NP, false, false, PAIR>);
   }
   return hipGetLastError();
 }
@@ -352,7 +385,9 @@ ChanSel chansel_all(int Np) {
   }
   const int S = Np / 16;
   for (int i = 0; i < S; ++i) c.sub[i] = static_cast<unsigned char>(i);
+  for (int i = 0; i < S / 2; ++i) c.pair[i] = static_cast<unsigned char>(i);
   c.nsub = S;
+  c.npair = S / 2;
   c.nch = Np;
   return c;
 }
@@ -369,6 +404,8 @@ ChanSel chansel_from_mask(int Np, const unsigned char* mask) {
   }
   for (int i = 0; i < S; ++i)
     if (used[i]) c.sub[c.nsub++] = static_cast<unsigned char>(i);
+  for (int i = 0; i < S / 2; ++i)
+    if (used[i] || used[i + S / 2]) c.pair[c.npair++] = static_cast<unsigned char>(i);
   return c;
 }
 
