@@ -1,7 +1,9 @@
 """CPU checks of the gfx950 code the SSCA kernels compile to (no GPU needed).
 
-* Every out-of-range-safe sample load is one 64-bit buffer load with the whole offset in the range-checked
-  VGPR operand; a split or narrowed load would read past the signal instead of the zero padding.
+* Every out-of-range-safe sample load is one 64-bit buffer load addressed through the range-checked VGPR
+  offset (plus, at most, an immediate offset, which the buffer range check includes: the checked offset is the
+  32-bit sum of both); a split or narrowed load would read past the signal instead of the zero padding, and a
+  scalar offset would escape the check.
 * The headline Stage-1 kernel (Np = 64, Np dividing M2, all strips) and the Stage-2 kernels do not spill
   registers.
 """
@@ -38,8 +40,10 @@ def test_sample_loads_are_single_64bit_range_checked(asm):
     assert loads
     for ins in loads:
         assert ins[0] == "buffer_load_dwordx2", ins
-        # operands: vdst, voffset, srsrc, soffset(0), offen; no immediate offset outside the range check
-        assert ins[-2:] == ["0", "offen"], ins
+        # operands: vdst, voffset, srsrc, soffset (0), offen [, offset:imm]
+        ops = [o.rstrip(",") for o in ins[1:]]
+        assert ops[3] == "0" and ops[4] == "offen", ins
+        assert len(ops) == 5 or (len(ops) == 6 and re.fullmatch(r"offset:\d+", ops[5])), ins
 
 
 def _spills(asm):

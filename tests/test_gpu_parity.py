@@ -150,6 +150,20 @@ def test_edge_energy_at_signal_ends(dev):
     assert rel(S, O.ssca(x, Np, w32(Np).astype(np.float64))) <= TOL_FP32
 
 
+def test_edge_energy_at_signal_ends_full_size(dev):
+    """The headline configuration (N = 2^20, Np = 64, Np dividing M2): frames that start before sample 0 or end
+    after sample N-1 read zeros there and the true samples elsewhere, on sampled strips."""
+    N, Np = 1 << 20, 64
+    x = np.zeros(N, np.complex128)
+    x[:100] = sg.noise(100, sg.rng_for(53, 2))
+    x[-100:] = sg.noise(100, sg.rng_for(53, 3))
+    S = scd.ssca(to_gpu(x, dev), Np).cpu().numpy()
+    w = w32(Np).astype(np.float64)
+    for k in (0, 17, 33, 63):
+        ref = O.ssca_strip(x, Np, w, k)
+        assert np.abs(S[k] - ref).max() <= TOL_FP32 * np.abs(ref).max(), k
+
+
 def test_determinism(dev):
     x = to_gpu(sg.qpsk(1 << 16, 0.1, 8, 5.0, sg.rng_for(54, 0)), dev)
     a = scd.ssca(x, 64)
