@@ -8,9 +8,10 @@ Prints one JSON line. `value` is SCD points/s = Np*N / (seconds per step) with x
 resident in HBM. `roofline` reports the dominant kernel's algorithmic HBM bytes per launch over its average
 event-timed duration against the 8 TB/s HBM peak. `cpu_baseline` times the FP64 oracle on this host
 (single-threaded numpy) over all 64 strips of the same signal, which also gives the error of every GPU form
-against it.
+against it. A `fam` object times the FFT accumulation method on the batch workload (16 signals of 16384
+samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline] [--no-fam]
        python bench.py --write-traffic FETCH_CSV WRITE_CSV   (no GPU: summarise two rocprofv3 --pmc runs of
        `bench.py --copy-calib --forms fp32`, one with FETCH_SIZE and one with WRITE_SIZE, into the committed
        per-launch HBM traffic of the SSCA kernels)
@@ -105,6 +106,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fam", action="store_true", help="skip the FAM batch measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB read + 256 MiB write elementwise kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -154,9 +156,10 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, mask, fb = SEL.ssca_learned(x, sel, win=win, out=lout)
+            _, mask, _ = SEL.ssca_learned(x, sel, win=win, out=lout, want_fallback=False)
         torch.cuda.synchronize()
         lms = (time.perf_counter() - t0) * 1e3 / args.steps
+        _, mask, fb = SEL.ssca_learned(x, sel, win=win, out=lout)
         m = mask.cpu().numpy().astype(bool)
         full = scd.ssca(x, Np, win=win)
         labels = SEL.strip_labels(full)[0].cpu().numpy()[0] > 0.5
@@ -207,6 +210,42 @@ def main():
             "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "source_digest": digest}
 
+    fam_line = None
+    if not args.no_fam:
+        # FAM on the batch workload: 16 signals of 16384 samples, Np = 256, L = 64, P = 256 (one scd_fam call:
+        # channelizer + pair/P-point-DFT kernels). Algorithmic bytes: x, X_T written and read, S written.
+        cf = W.cfg2()
+        fp = cf["fam"]
+        fNp, fL, fP = fp["Np"], fp["L"], fp["P"]
+        fB = cf["x"].shape[0]
+        fx = torch.from_numpy(cf["x"][:, :fP * fL].astype(np.complex64)).to(dev)
+        fw = torch.from_numpy(fp["win"].astype(np.float32)).to(dev)
+        fout = torch.empty(fB, fNp, fNp, fP, dtype=torch.complex64, device=dev)
+        for _ in range(args.warmup):
+            scd.fam(fx, fNp, fL, fP, win=fw, out=fout)
+        fev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            fev[i][0].record(stream)
+            scd.fam(fx, fNp, fL, fP, win=fw, out=fout)
+            fev[i][1].record(stream)
+        torch.cuda.synchronize()
+        fms = float(np.mean([e[0].elapsed_time(e[1]) for e in fev]))
+        fbytes = 8 * fB * fP * fL + 2 * 8 * fB * fNp * fP + 8 * fB * fNp * fNp * fP
+        fam_line = {"workload": f"FAM Np={fNp} L={fL} P={fP}, {fB} signals of {fP * fL} samples (batch recipe)",
+                    "ms_per_batch": round(fms, 5), "pts_per_s": round(fB * fNp * fNp * fP / (fms * 1e-3), 1),
+                    "roofline": {"bound": "hbm", "achieved": round(fbytes / (fms * 1e-3) / 1e9, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(fbytes / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "algorithmic_bytes": fbytes}}
+        if not args.no_cpu_baseline:
+            from oracle import scd_oracle as O
+
+            ref = O.fam(cf["x"][0, :fP * fL].astype(np.complex64).astype(np.complex128), fNp, fL, fP,
+                        fp["win"].astype(np.float32).astype(np.float64))
+            fam_line["max_err_vs_oracle_signal0"] = float(np.abs(fout[0].cpu().numpy() - ref).max() / np.abs(ref).max())
+        del fout
+
     cpu = None
     errs = {}
     if not args.no_cpu_baseline:
@@ -247,6 +286,8 @@ def main():
                                           if "fp32" in results else None),
                       "max_err_vs_oracle": errs.get(f)} for f, rr in results.items()},
     }
+    if fam_line is not None:
+        line["fam"] = fam_line
     if learned_info is not None:
         li = learned_info
         line["forms"]["learned"] = {
@@ -255,7 +296,7 @@ def main():
             "selected_pts_per_s": round(li["strips"] * N / (li["ms_per_step"] * 1e-3), 1),
             "fell_back": li["fell_back"], "active_strips": li["active_strips"],
             "recall_vs_full": li["recall_vs_full"], "max_err_vs_oracle": errs.get("learned"),
-            "note": "whole scd_ssca_learned call: features, MLP, selection (one readback), selected strips"}
+            "note": "whole scd_ssca_learned call: features, fused MLP + selection kernel, selected strips (asynchronous)"}
     print(json.dumps(line), flush=True)
 
 

@@ -210,12 +210,16 @@ int scd_adam_step(int n, float* params, const float* grads, float* m, float* v, 
 /* mask[b][k] = scores[b][k] >= theta; conf[b] = min_k max(s, 1 - s) (device arrays). */
 int scd_select(const float* scores, int Np, int batch, float theta, unsigned char* mask, float* conf, void* stream);
 
-/* SSCA of one signal restricted to the strips the selector picks. Runs the features, the MLP and the selection
- * on the GPU, reads the mask and confidence back (this call synchronises its stream once), then computes and
- * writes only the selected strips of out ([Np][N]; the other rows are left untouched). If the confidence is
- * below selector->conf_min the full SSCA runs instead, *fell_back is set to 1 and mask is set to all ones.
- * mask: device Np bytes (written). fell_back: host int. opts: precision (SCD_FP32 or SCD_SPLIT_BF16), stream,
- * workspace as scd_ssca_ex (batch must be 1). N must be a power of two in [2^14, 2^20]. Errors as scd_ssca_ex, plus SCD_ERR_MODEL. */
+/* SSCA of one signal restricted to the strips the selector picks (a library form; the paper has no selector).
+ * Everything runs on the GPU, in stream order: the features, one kernel that standardises them, runs the MLP,
+ * thresholds the scores at selector->theta, falls back to every strip when min_k max(s_k, 1 - s_k) is below
+ * selector->conf_min, and writes the selection to device memory; then Stage 1 and Stage 2 over the selected
+ * strips only (their grids cover every strip and skip the unselected ones, so the host never waits for the
+ * selection). Only the selected strips of out ([Np][N]) are written; the other rows are left untouched.
+ * mask: device Np bytes (written: 1 = computed). fell_back: host int, or NULL; when given, the call copies the
+ * fallback flag back and synchronises its stream once, at the end. selector->params must be 16-byte aligned.
+ * opts: precision (SCD_FP32 or SCD_SPLIT_BF16), stream, workspace as scd_ssca_ex (batch must be 1). N must be
+ * a power of two in [2^14, 2^20]. Errors as scd_ssca_ex, plus SCD_ERR_MODEL. */
 int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
                      unsigned char* mask, int* fell_back, const scd_opts* opts);
 

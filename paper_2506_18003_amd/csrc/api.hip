@@ -495,8 +495,10 @@ int scd_select(const float* scores, int Np, int batch, float theta, unsigned cha
 
 int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
                      unsigned char* mask, int* fell_back, const scd_opts* opts) {
-  if (!x || !win || !selector || !out || !mask || !fell_back) return fail(SCD_ERR_NULL, "NULL argument");
+  if (!x || !win || !selector || !out || !mask) return fail(SCD_ERR_NULL, "NULL argument");
   if (!selector->params || !selector->mu || !selector->sigma) return fail(SCD_ERR_MODEL, "selector has NULL arrays");
+  if (reinterpret_cast<uintptr_t>(selector->params) % 16 != 0)
+    return fail(SCD_ERR_MODEL, "selector params must be 16-byte aligned");
   if (selector->Np != Np) return fail(SCD_ERR_MODEL, "selector was trained for Np = %d, not %d", selector->Np, Np);
   if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_learned takes one signal per call");
   if (opts && opts->precision != SCD_FP32 && opts->precision != SCD_SPLIT_BF16)
@@ -505,7 +507,7 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
     return fail(SCD_ERR_SIZE, "the learned form needs N a power of two in [2^14, 2^20]");
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
   hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
-  // Selector scratch: features, standardised features, activations, logits, scores, confidence.
+  // Selector scratch: features, then (after the training-sized slots) confidence, fallback flag, selection.
   const scd::MlpLayout L = scd::mlp_layout(Np);
   int rc;
   float* f = nullptr;
@@ -521,47 +523,28 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
     if ((rc = grow(&g_dev[dev].sel, &g_dev[dev].sel_bytes, 4u * kSelScratchFloats, &p))) return rc;
     f = static_cast<float*>(p);
   }
-  float* fs = f + 2 * Np;
-  float* act = fs + 2 * Np;
-  float* z = act + 4 * scd::kHidden;
-  float* sc = z + Np;
-  float* conf = sc + Np;
+  float* conf = f + kSelScratchFloats - kSelStructFloats - 2;
+  int* dfell = reinterpret_cast<int*>(conf + 1);
+  scd::ChanSel* dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
   scd_opts fo{};
   fo.stream = stream;
   if ((rc = scd_features(x, N, Np, win, f, &fo))) return rc;
-  hipError_t e = scd::launch_standardize(f, selector->mu, selector->sigma, fs, 1, 2 * Np, stream);
-  if (e == hipSuccess) e = scd::launch_mlp_forward(Np, 1, selector->params, fs, act, z, sc, stream);
-  if (e == hipSuccess) e = scd::launch_select(sc, Np, 1, selector->theta, mask, conf, stream);
-  unsigned char hmask[256];
-  float hconf = 0.f;
-  if (e == hipSuccess) e = hipMemcpyAsync(hmask, mask, Np, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&hconf, conf, 4, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  hipError_t e = scd::launch_select_infer(f, selector->mu, selector->sigma, selector->params, Np, selector->theta,
+                                          selector->conf_min, mask, conf, dfell, dsel, stream);
   if (e != hipSuccess) return hip_fail(e, "selector");
-  scd::ChanSel hsel;
-  if (hconf < selector->conf_min) {
-    *fell_back = 1;
-    std::memset(hmask, 1, Np);
-    e = hipMemcpyAsync(mask, hmask, Np, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail(e, "mask update");
-    hsel = scd::chansel_all(Np);
-  } else {
-    *fell_back = 0;
-    hsel = scd::chansel_from_mask(Np, hmask);
-    if (hsel.nch == 0) return SCD_OK;
-  }
-  // The selection goes to device memory (after the selector scratch), where the kernels read it.
-  scd::ChanSel* dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
-  e = hipMemcpyAsync(dsel, &hsel, sizeof(hsel), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return hip_fail(e, "selection upload");
-  const scd::SelArg sel{dsel, hsel.nsub, hsel.npair, hsel.nch};
+  // The grids cover every subset and strip; the kernels read the selection from dsel and skip the rest.
+  const scd::SelArg sel{dsel, Np / 16, Np / 32, Np};
   scd_opts so{};
   if (opts) so = *opts;
   so.batch = 1;
   so.stream = stream;
-  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, &so, &sel);
+  if ((rc = ssca_common(SscaPart::kWhole, x, N, Np, win, out, &so, &sel))) return rc;
+  if (fell_back) {
+    e = hipMemcpyAsync(fell_back, dfell, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "fallback flag read-back");
+  }
+  return SCD_OK;
 }
 
 void scd_shutdown(void) {

@@ -233,6 +233,87 @@ __global__ __launch_bounds__(256) void select_kernel(const float* __restrict__ s
   if (tid == 0) conf[sig] = red[0];
 }
 
+__device__ __forceinline__ float bf16r(float v) { return static_cast<float>(static_cast<__bf16>(v)); }
+
+// out[o] = sum_i bf16(W[o][i]) in[i] + b[o] for o < nout, in FP32 (in[] already bf16-valued, in LDS).
+__device__ __forceinline__ float dense_row(const float* __restrict__ W, const float* in, int nin, int o) {
+  const float4* w = reinterpret_cast<const float4*>(W + static_cast<int64_t>(o) * nin);
+  float acc = 0.f;
+  for (int i = 0; i < nin / 4; ++i) {
+    const float4 v = w[i];
+    acc = fmaf(bf16r(v.x), in[4 * i], acc);
+    acc = fmaf(bf16r(v.y), in[4 * i + 1], acc);
+    acc = fmaf(bf16r(v.z), in[4 * i + 2], acc);
+    acc = fmaf(bf16r(v.w), in[4 * i + 3], acc);
+  }
+  return acc;
+}
+
+// Selector inference of one signal in one workgroup: standardised features -> MLP (every product of bf16-rounded
+// operands, FP32 accumulation, as in the GEMM kernels) -> strip scores -> mask, confidence, fallback and the
+// channel selection of the SSCA kernels. Thread o computes output o of each layer from its weight row.
+__global__ __launch_bounds__(256) void select_infer_kernel(const float* __restrict__ feat, const float* __restrict__ mu,
+                                                           const float* __restrict__ sigma,
+                                                           const float* __restrict__ params, int Np, float theta,
+                                                           float conf_min, unsigned char* __restrict__ mask,
+                                                           float* __restrict__ conf_out, int* __restrict__ fell,
+                                                           ChanSel* __restrict__ sel) {
+  __shared__ float xin[512];
+  __shared__ float h1[kHidden], h2[kHidden];
+  __shared__ float red[256];
+  __shared__ unsigned char keep[256];
+  const int tid = threadIdx.x;
+  const MlpLayout L = mlp_layout(Np);
+  for (int i = tid; i < L.in; i += 256) xin[i] = bf16r((feat[i] - mu[i]) / sigma[i]);
+  __syncthreads();
+  h1[tid] = bf16r(fmaxf(dense_row(params + L.W1, xin, L.in, tid) + params[L.b1 + tid], 0.f));
+  __syncthreads();
+  h2[tid] = bf16r(fmaxf(dense_row(params + L.W2, h1, kHidden, tid) + params[L.b2 + tid], 0.f));
+  __syncthreads();
+  float s = 0.f, c = 1.f;
+  if (tid < Np) {
+    const float z = dense_row(params + L.W3, h2, kHidden, tid) + params[L.b3 + tid];
+    s = 1.f / (1.f + expf(-z));
+    c = fmaxf(s, 1.f - s);
+  }
+  red[tid] = c;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] = fminf(red[tid], red[tid + st]);
+    __syncthreads();
+  }
+  const float conf = red[0];
+  const bool fb = conf < conf_min;
+  if (tid < Np) {
+    const unsigned char m = (fb || s >= theta) ? 1 : 0;
+    keep[tid] = m;
+    mask[tid] = m;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int S = Np / 16;
+    unsigned kb[8] = {};
+    bool used[16] = {};
+    int nch = 0, nsub = 0, npair = 0;
+    for (int k = 0; k < Np; ++k) {
+      if (!keep[k]) continue;
+      kb[k >> 5] |= 1u << (k & 31);
+      sel->ch[nch++] = static_cast<unsigned char>(k);
+      used[k % S] = true;  // strip k belongs to subset k mod S
+    }
+    for (int i = 0; i < S; ++i)
+      if (used[i]) sel->sub[nsub++] = static_cast<unsigned char>(i);
+    for (int i = 0; i < S / 2; ++i)
+      if (used[i] || used[i + S / 2]) sel->pair[npair++] = static_cast<unsigned char>(i);
+    for (int w = 0; w < 8; ++w) sel->keep[w] = kb[w];
+    sel->nch = nch;
+    sel->nsub = nsub;
+    sel->npair = npair;
+    *conf_out = conf;
+    *fell = fb ? 1 : 0;
+  }
+}
+
 inline dim3 blocks1(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
 
 template <bool TA, bool TB, int EPI>
@@ -244,20 +325,6 @@ hipError_t gemm(const float* A, int lda, const float* B, int ldb, float* C, floa
 }
 
 }  // namespace
-
-MlpLayout mlp_layout(int Np) {
-  MlpLayout L;
-  L.in = 2 * Np;
-  L.out = Np;
-  L.W1 = 0;
-  L.b1 = L.W1 + kHidden * L.in;
-  L.W2 = L.b1 + kHidden;
-  L.b2 = L.W2 + kHidden * kHidden;
-  L.W3 = L.b2 + kHidden;
-  L.b3 = L.W3 + Np * kHidden;
-  L.total = L.b3 + Np;
-  return L;
-}
 
 hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t s) {
   hipLaunchKernelGGL(acp_features_kernel, dim3(Np, nsig), dim3(256), 0, s, seg, Np, feat);
@@ -333,6 +400,15 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int 
                        float eps, hipStream_t s) {
   const float c1 = 1.f - powf(b1, static_cast<float>(t)), c2 = 1.f - powf(b2, static_cast<float>(t));
   hipLaunchKernelGGL(adam_kernel, blocks1(n), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_infer(const float* feat, const float* mu, const float* sigma, const float* params, int Np,
+                               float theta, float conf_min, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
+                               hipStream_t s) {
+  if (Np > 256 || 2 * Np > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(select_infer_kernel, dim3(1), dim3(256), 0, s, feat, mu, sigma, params, Np, theta, conf_min, mask,
+                     conf, fell, sel);
   return hipGetLastError();
 }
 

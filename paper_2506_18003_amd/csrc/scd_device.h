@@ -234,6 +234,21 @@ struct LdsLayout {
   }
 };
 
+// Block index -> (m2, unit) of a Stage-1 grid of M2 x units blocks (units a power of two): XCD x (blocks
+// b = x mod 8) takes m2 in [x M2/8, (x+1) M2/8) with the units of one m2 adjacent; plain order if M2 < 8.
+__device__ __forceinline__ void block_to_m2_unit(int M2, int m2shift, int& m2, int& u) {
+  const int b = blockIdx.x;
+  const int ushift = __builtin_ctz(gridDim.x >> m2shift);
+  if ((M2 & 7) == 0) {
+    const int idx = b >> 3;
+    m2 = (b & 7) * (M2 >> 3) + (idx >> ushift);
+    u = idx & ((1 << ushift) - 1);
+  } else {
+    m2 = b & (M2 - 1);
+    u = b >> m2shift;
+  }
+}
+
 struct NoLoad {};
 struct NoStore {};
 

@@ -20,10 +20,11 @@ constexpr int SCD_PREC_BF16 = 3;
 constexpr int SCD_PREC_FP16 = 4;
 constexpr int kMfmaPad = 256;  // zero samples on each side of the 16-bit copies of x
 
-// Which strips an SSCA launch computes (read by the kernels from device memory). Stage 1 runs the channel
-// subsets sub[0..nsub) (subset c holds the strips k = c (mod Np/16)), or, in its paired form, the subset pairs
-// pair[0..npair) (pair p holds subsets p and p + Np/32), and stores strip k only if bit k of keep is set;
-// stage 2 runs strips ch[0..nch).
+// Which strips an SSCA launch computes, built on the GPU and read by the kernels from device memory. Stage 1
+// runs the channel subsets sub[0..nsub) (subset c holds the strips k = c (mod Np/16)), or, in its paired
+// form, the subset pairs pair[0..npair) (pair p holds subsets p and p + Np/32), and stores strip k only if
+// bit k of keep is set; stage 2 runs strips ch[0..nch). Grids are sized for every subset and strip, and the
+// workgroups past the counts exit.
 struct ChanSel {
   unsigned keep[8];
   unsigned char sub[16];
@@ -31,12 +32,8 @@ struct ChanSel {
   unsigned char ch[256];
   int nsub, npair, nch;
 };
-// Every strip of an Np-channel SSCA.
-ChanSel chansel_all(int Np);
-// The strips with mask[k] != 0 (host array of Np bytes).
-ChanSel chansel_from_mask(int Np, const unsigned char* mask);
-// A selection as the launchers take it: the counts (host) and the ChanSel in device memory, read by the kernels
-// through the scalar cache; dev == nullptr means every strip (sub[i] = i, ch[k] = k, all kept).
+// A selection as the launchers take it: the grid sizes (host; the most units the selection can hold) and the
+// ChanSel in device memory; dev == nullptr means every strip (sub[i] = i, pair[i] = i, ch[k] = k, all kept).
 struct SelArg {
   const ChanSel* dev;
   int nsub, npair, nch;
@@ -75,7 +72,19 @@ constexpr int kHidden = 256;
 struct MlpLayout {  // offsets (floats) of the packed parameters [W1 b1 W2 b2 W3 b3]
   int in, out, W1, b1, W2, b2, W3, b3, total;
 };
-MlpLayout mlp_layout(int Np);
+__host__ __device__ inline MlpLayout mlp_layout(int Np) {
+  MlpLayout L;
+  L.in = 2 * Np;
+  L.out = Np;
+  L.W1 = 0;
+  L.b1 = L.W1 + kHidden * L.in;
+  L.W2 = L.b1 + kHidden;
+  L.b2 = L.W2 + kHidden * kHidden;
+  L.W3 = L.b2 + kHidden;
+  L.b3 = L.W3 + Np * kHidden;
+  L.total = L.b3 + Np;
+  return L;
+}
 // seg: [nsig][16][Np][1024] segment SSCAs -> feat [nsig][2 Np] (centred PSD, ACP).
 hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t stream);
 // S: [nsig][Np][N] -> labels [nsig][Np] (0/1), ratio [nsig][Np] (may be null).
@@ -91,5 +100,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int 
                        float eps, hipStream_t stream);
 hipError_t launch_select(const float* sc, int Np, int nsig, float theta, unsigned char* mask, float* conf,
                          hipStream_t stream);
+// Selector inference of one signal in one kernel: standardise feat [2 Np], MLP, strip mask (device Np bytes),
+// confidence, fallback to every strip when the confidence is below conf_min (fell = 1), and the ChanSel the
+// SSCA kernels read.
+hipError_t launch_select_infer(const float* feat, const float* mu, const float* sigma, const float* params, int Np,
+                               float theta, float conf_min, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
+                               hipStream_t stream);
 
 }  // namespace scd

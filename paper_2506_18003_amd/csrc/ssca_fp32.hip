@@ -48,8 +48,10 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 }
 
 // Stage 1. The flattened block index is mapped so that each of the 8 XCDs (which receive blocks round-robin)
-// walks a contiguous range of m2: the frames of neighbouring m2 overlap in all but one sample, so an XCD's
-// share of x stays in its L2. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
+// walks a contiguous range of m2, all channel subsets of one m2 next to each other: the frames of
+// neighbouring m2 overlap in all but one sample, so an XCD's share of x stays in its L2. With a selection in
+// device memory the grid covers every subset and the workgroups past the selected count exit at once, so
+// the host never needs to know the selection. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
 // a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2, with 256 threads per subset;
 // thread t of a subset owns frames m1 = t + 256 f (f < 4).
 //
@@ -95,12 +97,11 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   const int tid = threadIdx.x;
   const int half = PAIR ? (tid >> 8) : 0;
   const int t = tid & (kP1Threads - 1);
-  const int nblk = gridDim.x;
-  int lin = blockIdx.x;
-  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
-  const int cg = SEL ? (PAIR ? sel->pair[lin >> m2shift] : sel->sub[lin >> m2shift]) : (lin >> m2shift);
+  int m2, u;
+  block_to_m2_unit(M2, m2shift, m2, u);
+  if (SEL && u >= (PAIR ? sel->npair : sel->nsub)) return;
+  const int cg = SEL ? (PAIR ? sel->pair[u] : sel->sub[u]) : u;
   const int c = cg + half * (S / 2);  // this thread's subset
-  const int m2 = lin & (M2 - 1);
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
   const float2* rlo = tabs + kTabRotLo;
@@ -280,6 +281,7 @@ __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __re
   __shared__ float2 tw[1024];
   const int tid = threadIdx.x;
   const int mb = blockIdx.x;  // block of 16 consecutive m1'
+  if (sel && static_cast<int>(blockIdx.y) >= sel->nch) return;
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
   __syncthreads();
@@ -304,6 +306,7 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
   __shared__ float2 tw[1024];
   const int tid = threadIdx.x;
   const int mb = blockIdx.x;  // block of 16 consecutive m1'
+  if (sel && static_cast<int>(blockIdx.y) >= sel->nch) return;
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
   const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (1024 * 16);
@@ -376,38 +379,6 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int ba
 }
 
 }  // namespace
-
-ChanSel chansel_all(int Np) {
-  ChanSel c{};
-  for (int k = 0; k < Np; ++k) {
-    c.keep[k >> 5] |= 1u << (k & 31);
-    c.ch[k] = static_cast<unsigned char>(k);
-  }
-  const int S = Np / 16;
-  for (int i = 0; i < S; ++i) c.sub[i] = static_cast<unsigned char>(i);
-  for (int i = 0; i < S / 2; ++i) c.pair[i] = static_cast<unsigned char>(i);
-  c.nsub = S;
-  c.npair = S / 2;
-  c.nch = Np;
-  return c;
-}
-
-ChanSel chansel_from_mask(int Np, const unsigned char* mask) {
-  ChanSel c{};
-  const int S = Np / 16;
-  bool used[16] = {};
-  for (int k = 0; k < Np; ++k) {
-    if (!mask[k]) continue;
-    c.keep[k >> 5] |= 1u << (k & 31);
-    c.ch[c.nch++] = static_cast<unsigned char>(k);
-    used[k % S] = true;  // strip k belongs to subset k mod S
-  }
-  for (int i = 0; i < S; ++i)
-    if (used[i]) c.sub[c.nsub++] = static_cast<unsigned char>(i);
-  for (int i = 0; i < S / 2; ++i)
-    if (used[i] || used[i + S / 2]) c.pair[c.npair++] = static_cast<unsigned char>(i);
-  return c;
-}
 
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
                                   float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {

@@ -125,11 +125,10 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 5, lc = lane & 31;
-  const int nblk = gridDim.x;
-  int lin = blockIdx.x;
-  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
-  const int c = SEL ? sel->sub[lin >> m2shift] : (lin >> m2shift);
-  const int m2 = lin & (M2 - 1);
+  int m2, u;
+  block_to_m2_unit(M2, m2shift, m2, u);
+  if (SEL && u >= sel->nsub) return;
+  const int c = SEL ? sel->sub[u] : u;
   x += blockIdx.y * xbs;
   xhi += blockIdx.y * pbs;
   xlo += blockIdx.y * pbs;

@@ -195,8 +195,9 @@ class Selector:
         return c
 
 
-def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None):
-    """SSCA of one signal restricted to the strips the selector picks: (out, mask [Np] uint8, fell_back)."""
+def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None, want_fallback=True):
+    """SSCA of one signal restricted to the strips the selector picks: (out, mask [Np] uint8, fell_back).
+    With want_fallback=False the call stays asynchronous (no read-back) and fell_back is None."""
     torch = _torch()
     from . import _window, _check_x, PRECISIONS
     _check_x(x)
@@ -213,8 +214,9 @@ def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None):
     cs = sel.c_struct()
     with torch.cuda.device(x.device):
         _lib.check(_lib.lib().scd_ssca_learned(x.data_ptr(), N, Np, w.data_ptr(), ctypes.byref(cs), out.data_ptr(),
-                                               mask.data_ptr(), ctypes.byref(fb), ctypes.byref(o)))
-    return out, mask, bool(fb.value)
+                                               mask.data_ptr(), ctypes.byref(fb) if want_fallback else None,
+                                               ctypes.byref(o)))
+    return out, mask, (bool(fb.value) if want_fallback else None)
 
 
 class Trainer:

@@ -129,4 +129,7 @@ def test_learned_entry_errors(L):
     sel.params, sel.mu, sel.sigma = 0x1000, 0x2000, 0x3000
     assert L.scd_ssca_learned(_fake(X), 1 << 16, 32, _fake(W), ctypes.byref(sel), _fake(O), _fake(O + 8),
                               ctypes.byref(fb), None) == _lib.SCD_ERR_MODEL
+    sel.params = 0x1004  # parameters must be 16-byte aligned
+    assert L.scd_ssca_learned(_fake(X), 1 << 16, 64, _fake(W), ctypes.byref(sel), _fake(O), _fake(O + 8),
+                              None, None) == _lib.SCD_ERR_MODEL
     assert L.scd_adam_step(0, _fake(X), _fake(W), _fake(O), _fake(O), 1, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.SCD_ERR_SIZE
