@@ -68,9 +68,8 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 //
 // The M1 = 1024-point DFT over m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle
 // omega_1024^{t r}, and a 256-point DFT over t in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its
-// last radix stage stores to HBM, multiplying by the rotation factor omega_N^{m2 m1'} (and by the
-// down-conversion factor omega_Np^{(k m2) mod Np}, which does not depend on m1 when Np divides M2), built per
-// butterfly as a base times a per-block step table.
+// last radix stage stores to HBM, multiplying by the rotation factor omega_N^{m2 m1'} from a per-workgroup
+// LDS table.
 template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR>
 __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) void ssca_pass1_fp32(
     const float2* __restrict__ x, int N, int M2, int m2shift, const float2* __restrict__ hcg,
@@ -90,8 +89,8 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   static_assert(2 * kUBuf <= kXchgFloats, "fold buffers must fit in the exchange buffer");
   static_assert(!PAIR || NT % 2 == 0, "a subset pair needs Np >= 32");
   __shared__ float2 buf[NH * kXchgFloats];
-  __shared__ float2 tw[1024];
-  __shared__ float2 stp[16];
+  __shared__ float2 tw[kSeq];   // omega_256^e
+  __shared__ float2 rot[kM1];   // rotation factors omega_N^{m2 m1'} of this m2
   __shared__ float2 rt[NP];
 
   const int tid = threadIdx.x;
@@ -109,18 +108,22 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   const auto xr = make_rsrc(x, N * 8);
   const int hishift = 10 - m2shift;
 
-  for (int i = tid; i < 1024; i += NTH) tw[i] = tabs[kTabTw1024 + i];
-  for (int i = tid; i < NP; i += NTH) rt[i] = tabs[kTabRoots + i];
-  if (tid < 16) {
-    const float2* tw_g = tabs + kTabTw1024;
-    stp[tid] = rot_factor(rlo, tw_g, 64 * m2 * tid, hishift);
-  }
+  const float2* tw_g = tabs + kTabTw1024;
+  for (int i = tid; i < kSeq; i += NTH) tw[i] = tw_g[4 * i];
+  for (int i = tid; i < kM1; i += NTH) rot[i] = rot_factor(rlo, tw_g, m2 * i, hishift);
+  if constexpr (!PHASE_BY_M2)
+    for (int i = tid; i < NP; i += NTH) rt[i] = tabs[kTabRoots + i];
 
   const int j0 = tid & 15, fi = tid >> 4;
   float2 hl[NT];
 #pragma unroll
   for (int j1 = 0; j1 < NT; ++j1) hl[j1] = hc[j0 + 16 * j1];
-  const float2 w32 = tabs[kTabTw1024 + 32 * j0];  // omega_32^{j0}
+  const float2 w32 = tw_g[32 * j0];  // omega_32^{j0}
+  // When Np divides M2 the down-conversion factor omega_Np^{(c + S k') m2} does not depend on the frame. Its
+  // k'-dependent part omega_16^{k' m2} is a cyclic shift of the 16-point DFT's input by m2, applied by storing
+  // residue j0 at column (j0 + m2) mod 16; the constant part omega_Np^{c m2} goes into conj(x[n]).
+  const int jcol = PHASE_BY_M2 ? ((j0 + m2) & 15) : j0;
+  const float2 cphase = PHASE_BY_M2 ? tabs[kTabRoots + ((c * m2) & (NP - 1))] : make_float2(1.f, 0.f);
   // Round g folds frames m1 = FPR g + fi; its NT samples sit at x[base + 16 j1].
   const int base0 = fi * M2 + m2 - D + j0;
   float2 ring[PF][NT];
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
       const int g = RPG * f + r;
-      const int row = (FPR * r + fi) * kURow + j0;
+      const int row = (FPR * r + fi) * kURow + jcol;
       if constexpr (PAIR) {
         float2 ea = cmul(hl[0], ring[g % PF][0]);
         float2 eb = cmul(hl[1], ring[g % PF][1]);
@@ -165,10 +168,11 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     dft16(u);
     const int n = (t + 256 * f) * M2 + m2;
     const float2 xn = load_c64(xr, n);
+    const float2 xp = cmulc(xn, cphase);  // x[n] conj(omega_Np^{c m2})
 #pragma unroll
     for (int kp = 0; kp < 16; ++kp) {
       if constexpr (PHASE_BY_M2) {
-        col[f][kp] = cmulc(u[kp], xn);
+        col[f][kp] = cmulc(u[kp], xp);
       } else {
         const int k = c + S * kp;
         col[f][kp] = cmul(u[kp], cmulc(rt[(k * n) & (NP - 1)], xn));
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   }
 
   // 4-point DFT over f and twiddle omega_1024^{t r}: col[r][k'] now holds residue r of channel k'.
-  const float2 t1 = tw[t], t2 = tw[2 * t], t3 = tw[3 * t];
+  const float2 t1 = tw_g[t], t2 = tw_g[2 * t], t3 = tw_g[3 * t];
 #pragma unroll
   for (int kp = 0; kp < 16; ++kp) {
     float2 a[4] = {col[0][kp], col[1][kp], col[2][kp], col[3][kp]};
@@ -201,15 +205,12 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i.
     auto st = [&](int b, int m, float2 v) {
       const int k = c + S * (8 * h + (b >> 2));
-      const int rj = (b & 3) + 4 * (m & 15);
-      float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
-      if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
-      const int i = m >> 4;
+      const int m1p = (b & 3) + 4 * (m & 15) + 64 * (m >> 4);
       if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
-        st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+        st1_nt(T + ((k * (kM1 / 16) + (m1p >> 4)) * M2 + m2) * 16 + (m1p & 15), cmul(v, rot[m1p]));
     };
     NoLoad ld;
-    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>>(xb, tw, t, ld, st);
+    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);
   }
 }
 
