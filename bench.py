@@ -5,8 +5,10 @@ rotation) and Stage 2 (M2-point DFT), exactly the kernels scd_ssca runs, called 
 HIP events on the launch stream time each kernel inside the timed region.
 
 Prints one JSON line. `value` is SCD points/s = Np*N / (seconds per step) with x, window and output already
-resident in HBM. `roofline` reports the dominant kernel's algorithmic HBM bytes per launch over its average
-event-timed duration against the 8 TB/s HBM peak. `cpu_baseline` times the FP64 oracle on this host
+resident in HBM. `roofline` reports the dominant kernel (longest average event-timed duration) against the
+ceiling its arithmetic intensity puts it under: algorithmic flops against the 78.6 TFLOP/s FP32 vector peak
+when flops per algorithmic HBM byte exceed the ridge point (Stage 1), algorithmic HBM bytes against 8 TB/s
+otherwise (Stage 2); `per_kernel` gives both kernels both ways. `cpu_baseline` times the FP64 oracle on this host
 (single-threaded numpy) over all 64 strips of the same signal, which also gives the error of every GPU form
 against it. A `fam` object times the FFT accumulation method on the batch workload (16 signals of 16384
 samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes.
@@ -32,7 +34,10 @@ if ROOT not in sys.path:
 METRIC = "SCD pts/s, SSCA N=2^20 N'=64: FP32 vs split-BF16 vs learned strips"
 PAPER_PTS_PER_S = 2 ** 26 / 0.114  # VCK5000, 114 ms per SSCA estimate at N=2^20, N_P=64 (Table III)
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("scd_device.h", "ssca_fp32.hip", "ssca_mfma.hip")
+# FP32 vector peak without packed FP32 instructions (the library is built without them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+KERNEL_SOURCES = ("scd_device.h", "scd_launch.h", "ssca_fp32.hip")  # the FP32 SSCA kernels
 
 
 def source_digest(files=KERNEL_SOURCES) -> str:
@@ -190,25 +195,44 @@ def main():
                              step_ms_p10=tot[len(tot) // 10], step_ms_p50=tot[len(tot) // 2],
                              step_ms_p90=tot[(9 * len(tot)) // 10], out=out.cpu().numpy())
 
-    # Algorithmic HBM bytes per launch (one signal): pass 1 reads x and writes the intermediate; pass 2 reads
-    # and writes Np*N complex values.
+    # Algorithmic HBM bytes and flops per launch (one signal). Pass 1 reads x and writes the intermediate;
+    # pass 2 reads and writes Np*N complex values. Flops follow the paper's convention (5 n log2 n per n-point
+    # FFT, 6 per complex multiply, 2 per real window tap): pass 1 = the Np-point channelizer FFT of every frame,
+    # the window, the down-conversion, the channel-data product, the M1-point FFTs and the rotation; pass 2 =
+    # the M2-point FFTs.
+    lg = lambda v: v.bit_length() - 1
+    M1, M2 = 1024, N // 1024
     b1 = 8 * N + 8 * Np * N
     b2 = 2 * 8 * Np * N
+    f1 = N * 5 * Np * lg(Np) + 2 * Np * N + 3 * 6 * Np * N + Np * M2 * 5 * M1 * lg(M1)
+    f2 = Np * M1 * 5 * M2 * lg(M2)
     main_form = forms[0]
     r = results[main_form]
     digest = source_digest()
-    kern = {"ssca_pass1": (b1, r["pass1_ms"]), "ssca_pass2": (b2, r["pass2_ms"])}
-    dom = max(kern, key=lambda k: kern[k][1])
-    dbytes, dms = kern[dom]
-    achieved = dbytes / (dms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, digest),
-            "algorithmic_bytes": dbytes, "avg_ms": round(dms, 5),
-            "per_kernel": {k: {"avg_ms": round(v[1], 5), "algorithmic_bytes": v[0],
-                               "GB/s": round(v[0] / (v[1] * 1e-3) / 1e9, 1)} for k, v in kern.items()},
+    kern = {"ssca_pass1": (b1, f1, r["pass1_ms"]), "ssca_pass2": (b2, f2, r["pass2_ms"])}
+    ridge = VALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS  # flop/byte where the two ceilings meet
+
+    def kernel_roof(name):
+        nb, nf, ms = kern[name]
+        if nf / nb > ridge:  # compute side of the roofline: FP32 vector ALU
+            ach = nf / (ms * 1e-3) / 1e12
+            return {"bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / VALU_PEAK_TFLOPS, 4)}
+        ach = nb / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+
+    dom = max(kern, key=lambda k: kern[k][2])
+    roof = dict(kernel_roof(dom), kernel=dom, traffic=measured_traffic(dom, digest),
+                algorithmic_bytes=kern[dom][0], algorithmic_flops=kern[dom][1], avg_ms=round(kern[dom][2], 5))
+    roof.update({
+            "per_kernel": {k: dict(kernel_roof(k), avg_ms=round(v[2], 5), algorithmic_bytes=v[0],
+                                   algorithmic_flops=v[1], hbm_GBs=round(v[0] / (v[2] * 1e-3) / 1e9, 1),
+                                   hbm_frac=round(v[0] / (v[2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                           for k, v in kern.items()},
             "B_2p_frac": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "source_digest": digest}
+            "source_digest": digest})
 
     fam_line = None
     if not args.no_fam:

@@ -100,7 +100,7 @@ int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, float2** out) {
     return SCD_OK;
   }
   float2* t = nullptr;
-  hipError_t e = hipMalloc(&t, sizeof(float2) * (scd::kTabSize + scd::kHcFloats));
+  hipError_t e = hipMalloc(&t, sizeof(float2) * scd::kTabSize);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SCD_ERR_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
@@ -268,7 +268,6 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   DevState& st = g_dev[dev];
   float2* tabs;
   if ((rc = get_tables(st, N, Np, r.stream, &tabs))) return rc;
-  float2* hc = tabs + scd::kTabSize;
   const float2* ic = reinterpret_cast<const float2*>(in);
   float2* oc = reinterpret_cast<float2*>(dst);
   const int n = static_cast<int>(N);
@@ -276,7 +275,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   const scd::SelArg sel = selp ? *selp : scd::selarg_all(Np);
   // Stage 1 in the requested precision, for nb signals.
   auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
-    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, hc, T, nb, r.xs, tbs, sel, r.stream);
+    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, T, nb, r.xs, tbs, sel, r.stream);
     void* aux = nullptr;
     if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
     return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, sel, r.stream);
@@ -393,6 +392,34 @@ int scd_mlp_param_count(int Np) {
   return scd::mlp_layout(Np).total;
 }
 
+namespace {
+// Segment SSCAs and the feature reduction of `batch` signals (checked arguments, library lock held).
+int features_impl(const float* x, int64_t N, int Np, const float* win, float* feat, int batch, int64_t xs,
+                  hipStream_t stream, bool centre) {
+  int rc, dev;
+  if ((rc = current_device(&dev))) return rc;
+  DevState& st = g_dev[dev];
+  float2* tabs;
+  if ((rc = get_tables(st, 1024, Np, stream, &tabs))) return rc;
+  const size_t segb = 8u * 16u * static_cast<size_t>(Np) * 1024u;
+  void* lrn;
+  if ((rc = get_lrn(st, segb, &lrn))) return rc;
+  float2* seg = static_cast<float2*>(lrn);
+  const scd::SelArg sel = scd::selarg_all(Np);
+  const float2* xc = reinterpret_cast<const float2*>(x);
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < batch && e == hipSuccess; ++b) {
+    // 16 segments of 1024 samples, each an SSCA of its own (zero outside the segment).
+    e = scd::launch_ssca_pass1_fp32(xc + b * xs, 1024, Np, win, tabs, seg, 16, N / 16,
+                                    static_cast<int64_t>(Np) * 1024, sel, stream);
+    if (e == hipSuccess)
+      e = scd::launch_acp_features(seg, Np, 1, feat + static_cast<size_t>(b) * 2 * Np, stream, centre);
+  }
+  if (e != hipSuccess) return hip_fail(e, "feature launch");
+  return SCD_OK;
+}
+}  // namespace
+
 int scd_features(const float* x, int64_t N, int Np, const float* win, float* feat, const scd_opts* opts) {
   if (!x || !win || !feat) return fail(SCD_ERR_NULL, "x, win and feat must be non-NULL");
   if (!is_pow2(N) || N < (1 << 14) || N > (1 << 20))
@@ -407,26 +434,7 @@ int scd_features(const float* x, int64_t N, int Np, const float* win, float* fea
   if ((rc = check_device_range(x, xb, "x"))) return rc;
   if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
   if ((rc = check_device_range(feat, 4u * static_cast<size_t>(2 * Np) * r.batch, "feat"))) return rc;
-  int dev;
-  if ((rc = current_device(&dev))) return rc;
-  DevState& st = g_dev[dev];
-  float2* tabs;
-  if ((rc = get_tables(st, 1024, Np, r.stream, &tabs))) return rc;
-  const size_t segb = 8u * 16u * static_cast<size_t>(Np) * 1024u;
-  void* lrn;
-  if ((rc = get_lrn(st, segb, &lrn))) return rc;
-  float2* seg = static_cast<float2*>(lrn);
-  const scd::SelArg sel = scd::selarg_all(Np);
-  const float2* xc = reinterpret_cast<const float2*>(x);
-  hipError_t e = hipSuccess;
-  for (int b = 0; b < r.batch && e == hipSuccess; ++b) {
-    // 16 segments of 1024 samples, each an SSCA of its own (zero outside the segment).
-    e = scd::launch_ssca_pass1_fp32(xc + b * r.xs, 1024, Np, win, tabs, tabs + scd::kTabSize, seg, 16, N / 16,
-                                    static_cast<int64_t>(Np) * 1024, sel, r.stream);
-    if (e == hipSuccess) e = scd::launch_acp_features(seg, Np, 1, feat + static_cast<size_t>(b) * 2 * Np, r.stream);
-  }
-  if (e != hipSuccess) return hip_fail(e, "feature launch");
-  return SCD_OK;
+  return features_impl(x, N, Np, win, feat, r.batch, r.xs, r.stream, true);
 }
 
 int scd_strip_labels(const float* S, int64_t N, int Np, float* labels, float* ratio, const scd_opts* opts) {
@@ -526,11 +534,16 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
   float* conf = f + kSelScratchFloats - kSelStructFloats - 2;
   int* dfell = reinterpret_cast<int*>(conf + 1);
   scd::ChanSel* dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
-  scd_opts fo{};
-  fo.stream = stream;
-  if ((rc = scd_features(x, N, Np, win, f, &fo))) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = check_device_range(x, 8u * static_cast<size_t>(N), "x"))) return rc;
+    if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
+    // Raw features: the first MLP layer centres the PSD part itself.
+    if ((rc = features_impl(x, N, Np, win, f, 1, N, stream, false))) return rc;
+  }
+  float* act = f + 2 * 256;  // activations and scores: 2 * 256 + Np floats
   hipError_t e = scd::launch_select_infer(f, selector->mu, selector->sigma, selector->params, Np, selector->theta,
-                                          selector->conf_min, mask, conf, dfell, dsel, stream);
+                                          selector->conf_min, act, mask, conf, dfell, dsel, stream);
   if (e != hipSuccess) return hip_fail(e, "selector");
   // The grids cover every subset and strip; the kernels read the selection from dsel and skip the rest.
   const scd::SelArg sel{dsel, Np / 16, Np / 32, Np};

@@ -235,83 +235,130 @@ __global__ __launch_bounds__(256) void select_kernel(const float* __restrict__ s
 
 __device__ __forceinline__ float bf16r(float v) { return static_cast<float>(static_cast<__bf16>(v)); }
 
-// out[o] = sum_i bf16(W[o][i]) in[i] + b[o] for o < nout, in FP32 (in[] already bf16-valued, in LDS).
-__device__ __forceinline__ float dense_row(const float* __restrict__ W, const float* in, int nin, int o) {
-  const float4* w = reinterpret_cast<const float4*>(W + static_cast<int64_t>(o) * nin);
-  float acc = 0.f;
-  for (int i = 0; i < nin / 4; ++i) {
-    const float4 v = w[i];
-    acc = fmaf(bf16r(v.x), in[4 * i], acc);
-    acc = fmaf(bf16r(v.y), in[4 * i + 1], acc);
-    acc = fmaf(bf16r(v.z), in[4 * i + 2], acc);
-    acc = fmaf(bf16r(v.w), in[4 * i + 3], acc);
-  }
-  return acc;
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
 }
 
-// Selector inference of one signal in one workgroup: standardised features -> MLP (every product of bf16-rounded
-// operands, FP32 accumulation, as in the GEMM kernels) -> strip scores -> mask, confidence, fallback and the
-// channel selection of the SSCA kernels. Thread o computes output o of each layer from its weight row.
-__global__ __launch_bounds__(256) void select_infer_kernel(const float* __restrict__ feat, const float* __restrict__ mu,
-                                                           const float* __restrict__ sigma,
-                                                           const float* __restrict__ params, int Np, float theta,
-                                                           float conf_min, unsigned char* __restrict__ mask,
-                                                           float* __restrict__ conf_out, int* __restrict__ fell,
-                                                           ChanSel* __restrict__ sel) {
-  __shared__ float xin[512];
-  __shared__ float h1[kHidden], h2[kHidden];
-  __shared__ float red[256];
-  __shared__ unsigned char keep[256];
-  const int tid = threadIdx.x;
-  const MlpLayout L = mlp_layout(Np);
-  for (int i = tid; i < L.in; i += 256) xin[i] = bf16r((feat[i] - mu[i]) / sigma[i]);
-  __syncthreads();
-  h1[tid] = bf16r(fmaxf(dense_row(params + L.W1, xin, L.in, tid) + params[L.b1 + tid], 0.f));
-  __syncthreads();
-  h2[tid] = bf16r(fmaxf(dense_row(params + L.W2, h1, kHidden, tid) + params[L.b2 + tid], 0.f));
-  __syncthreads();
-  float s = 0.f, c = 1.f;
-  if (tid < Np) {
-    const float z = dense_row(params + L.W3, h2, kHidden, tid) + params[L.b3 + tid];
-    s = 1.f / (1.f + expf(-z));
-    c = fmaxf(s, 1.f - s);
+// One dense layer of selector inference, spread over the GPU: wave w of block b computes row o = 4 b + w,
+// out[o] = act(sum_i bf16(W[o][i]) in[i] + b[o]) with FP32 accumulation. Its lanes read 64 consecutive weights
+// per load (whole 256-byte runs, all NIN/64 loads in flight) and the row sum is reduced across the wave.
+// FIRST: in = bf16(standardised features) computed here from the raw features (PSD not yet centred: each wave
+// subtracts the mean PSD itself), mu and sigma; otherwise in is the previous layer's output (already
+// bf16-valued). ACT: 0 = ReLU then bf16 rounding (the next layer's operand), 1 = sigmoid.
+template <int NIN, bool FIRST, int ACT>
+__global__ __launch_bounds__(256) void mlp_infer_layer_kernel(const float* __restrict__ W, const float* __restrict__ bias,
+                                                              const float* __restrict__ in,
+                                                              const float* __restrict__ mu,
+                                                              const float* __restrict__ sigma, int nout,
+                                                              float* __restrict__ out) {
+  constexpr int C = NIN >= 64 ? NIN / 64 : 1;
+  const int lane = threadIdx.x & 63;
+  const int o = 4 * blockIdx.x + (threadIdx.x >> 6);
+  if (o >= nout) return;
+  const bool live = NIN >= 64 || lane < NIN;
+  float wv[C], xv[C];
+#pragma unroll
+  for (int cc = 0; cc < C; ++cc) wv[cc] = live ? W[static_cast<int64_t>(o) * NIN + 64 * cc + lane] : 0.f;
+  float mean = 0.f;
+  if constexpr (FIRST) {
+    constexpr int NPF = NIN / 2;  // PSD entries
+    float ps = 0.f;
+    for (int i = lane; i < NPF; i += 64) ps += in[i];
+    mean = wave_sum(ps) / static_cast<float>(NPF);
   }
-  red[tid] = c;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st) red[tid] = fminf(red[tid], red[tid + st]);
-    __syncthreads();
+#pragma unroll
+  for (int cc = 0; cc < C; ++cc) {
+    const int i = 64 * cc + lane;
+    float v = 0.f;
+    if (live) v = FIRST ? bf16r((in[i] - (i < NIN / 2 ? mean : 0.f) - mu[i]) / sigma[i]) : in[i];
+    xv[cc] = v;
   }
-  const float conf = red[0];
+  float acc = 0.f;
+#pragma unroll
+  for (int cc = 0; cc < C; ++cc) acc = fmaf(bf16r(wv[cc]), xv[cc], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    acc += bias[o];
+    out[o] = (ACT == 0) ? bf16r(fmaxf(acc, 0.f)) : 1.f / (1.f + expf(-acc));
+  }
+}
+
+// Strip selection of one signal from its scores: mask, confidence min_k max(s_k, 1 - s_k), fallback to every
+// strip below conf_min, and the channel selection the SSCA kernels read (strip list in increasing k from wave
+// ballots and per-wave counts, subset and pair lists from the kept strips).
+template <int NP>
+__global__ __launch_bounds__(256) void select_finish_kernel(const float* __restrict__ sc, float theta, float conf_min,
+                                                            unsigned char* __restrict__ mask,
+                                                            float* __restrict__ conf_out, int* __restrict__ fell,
+                                                            ChanSel* __restrict__ sel) {
+  __shared__ float red[4];
+  __shared__ int wcnt[4];
+  __shared__ unsigned long long wbits[4];
+  __shared__ unsigned char keep[NP];
+  __shared__ unsigned char used[16];
+  constexpr int S = NP / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const float s = tid < NP ? sc[tid] : 0.5f;
+  float c = tid < NP ? fmaxf(s, 1.f - s) : 1.f;
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) c = fminf(c, __shfl_xor(c, m, 64));
+  if (lane == 0) red[w] = c;
+  __syncthreads();
+  const float conf = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
   const bool fb = conf < conf_min;
-  if (tid < Np) {
-    const unsigned char m = (fb || s >= theta) ? 1 : 0;
-    keep[tid] = m;
-    mask[tid] = m;
+  const bool kp = tid < NP && (fb || s >= theta);
+  if (tid < NP) {
+    keep[tid] = kp ? 1 : 0;
+    mask[tid] = kp ? 1 : 0;
+  }
+  const unsigned long long bal = __ballot(kp);
+  if (lane == 0) {
+    wcnt[w] = __popcll(bal);
+    wbits[w] = bal;
+  }
+  __syncthreads();
+  int base = 0;
+  for (int i = 0; i < w; ++i) base += wcnt[i];
+  if (kp) sel->ch[base + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<unsigned char>(tid);
+  if (tid < 8) sel->keep[tid] = static_cast<unsigned>(wbits[tid >> 1] >> (32 * (tid & 1)));
+  if (tid < S) {  // subset tid holds the strips k = tid (mod S)
+    unsigned char u = 0;
+    for (int k = tid; k < NP; k += S) u |= keep[k];
+    used[tid] = u;
   }
   __syncthreads();
   if (tid == 0) {
-    const int S = Np / 16;
-    unsigned kb[8] = {};
-    bool used[16] = {};
-    int nch = 0, nsub = 0, npair = 0;
-    for (int k = 0; k < Np; ++k) {
-      if (!keep[k]) continue;
-      kb[k >> 5] |= 1u << (k & 31);
-      sel->ch[nch++] = static_cast<unsigned char>(k);
-      used[k % S] = true;  // strip k belongs to subset k mod S
-    }
+    int nsub = 0, npair = 0;
     for (int i = 0; i < S; ++i)
       if (used[i]) sel->sub[nsub++] = static_cast<unsigned char>(i);
     for (int i = 0; i < S / 2; ++i)
       if (used[i] || used[i + S / 2]) sel->pair[npair++] = static_cast<unsigned char>(i);
-    for (int w = 0; w < 8; ++w) sel->keep[w] = kb[w];
-    sel->nch = nch;
+    sel->nch = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     sel->nsub = nsub;
     sel->npair = npair;
     *conf_out = conf;
     *fell = fb ? 1 : 0;
   }
+}
+
+template <int NP>
+hipError_t select_infer(const float* feat, const float* mu, const float* sigma, const float* params, float theta,
+                        float conf_min, float* h, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
+                        hipStream_t s) {
+  const MlpLayout L = mlp_layout(NP);
+  float* h1 = h;
+  float* h2 = h + kHidden;
+  float* sc = h + 2 * kHidden;
+  hipLaunchKernelGGL((mlp_infer_layer_kernel<2 * NP, true, 0>), dim3(kHidden / 4), dim3(256), 0, s, params + L.W1,
+                     params + L.b1, feat, mu, sigma, kHidden, h1);
+  hipLaunchKernelGGL((mlp_infer_layer_kernel<kHidden, false, 0>), dim3(kHidden / 4), dim3(256), 0, s, params + L.W2,
+                     params + L.b2, h1, mu, sigma, kHidden, h2);
+  hipLaunchKernelGGL((mlp_infer_layer_kernel<kHidden, false, 1>), dim3(NP / 4), dim3(256), 0, s, params + L.W3,
+                     params + L.b3, h2, mu, sigma, NP, sc);
+  hipLaunchKernelGGL(select_finish_kernel<NP>, dim3(1), dim3(256), 0, s, sc, theta, conf_min, mask, conf, fell, sel);
+  return hipGetLastError();
 }
 
 inline dim3 blocks1(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
@@ -326,9 +373,9 @@ hipError_t gemm(const float* A, int lda, const float* B, int ldb, float* C, floa
 
 }  // namespace
 
-hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t s) {
+hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t s, bool centre) {
   hipLaunchKernelGGL(acp_features_kernel, dim3(Np, nsig), dim3(256), 0, s, seg, Np, feat);
-  hipLaunchKernelGGL(centre_psd_kernel, dim3(nsig), dim3(256), 0, s, feat, Np);
+  if (centre) hipLaunchKernelGGL(centre_psd_kernel, dim3(nsig), dim3(256), 0, s, feat, Np);
   return hipGetLastError();
 }
 
@@ -404,12 +451,16 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int 
 }
 
 hipError_t launch_select_infer(const float* feat, const float* mu, const float* sigma, const float* params, int Np,
-                               float theta, float conf_min, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
-                               hipStream_t s) {
-  if (Np > 256 || 2 * Np > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(select_infer_kernel, dim3(1), dim3(256), 0, s, feat, mu, sigma, params, Np, theta, conf_min, mask,
-                     conf, fell, sel);
-  return hipGetLastError();
+                               float theta, float conf_min, float* h, unsigned char* mask, float* conf, int* fell,
+                               ChanSel* sel, hipStream_t s) {
+  switch (Np) {
+    case 16: return select_infer<16>(feat, mu, sigma, params, theta, conf_min, h, mask, conf, fell, sel, s);
+    case 32: return select_infer<32>(feat, mu, sigma, params, theta, conf_min, h, mask, conf, fell, sel, s);
+    case 64: return select_infer<64>(feat, mu, sigma, params, theta, conf_min, h, mask, conf, fell, sel, s);
+    case 128: return select_infer<128>(feat, mu, sigma, params, theta, conf_min, h, mask, conf, fell, sel, s);
+    case 256: return select_infer<256>(feat, mu, sigma, params, theta, conf_min, h, mask, conf, fell, sel, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_select(const float* sc, int Np, int nsig, float theta, unsigned char* mask, float* conf,

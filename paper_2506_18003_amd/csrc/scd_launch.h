@@ -10,7 +10,6 @@ constexpr int kTabTw1024 = 0;     // omega_1024^j, j < 1024
 constexpr int kTabRotLo = 1024;   // omega_N^j,    j < 1024 (SSCA rotation factors, low part)
 constexpr int kTabRoots = 2048;   // omega_Np^e,   e < Np   (down-conversion factors)
 constexpr int kTabSize = 2048 + 256;
-constexpr int kHcFloats = 16 * 256;  // complex windows of every channel subset (S * Np <= 4096)
 
 // Channelizer precisions (values of scd_precision in scd.h).
 constexpr int SCD_PREC_FP32 = 0;
@@ -43,12 +42,10 @@ inline SelArg selarg_all(int Np) { return SelArg{nullptr, Np / 16, Np / 32, Np};
 hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 
 // SSCA Stage 1 (channelizer + CDP + M1-point DFT + rotation) of `batch` signals. x: [batch][N] at stride xbs;
-// T: [batch] blocked intermediates [Np][M1/16][M2][16] at stride tbs (float2 elements). With N == 1024 the
-// intermediate layout equals the output layout [Np][N]. hc: kHcFloats float2 of device scratch that this call
-// fills with the subsets' complex windows before stage 1 reads them.
-hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
-                                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel,
-                                  hipStream_t stream);
+// win: device float[Np]; T: [batch] blocked intermediates [Np][M1/16][M2][16] at stride tbs (float2 elements).
+// With N == 1024 the intermediate layout equals the output layout [Np][N].
+hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* T,
+                                  int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t stream);
 
 // SSCA Stage 1 with the channelizer on MFMA in 16-bit (split or plain) precision, Np <= 128. scratch: device
 // memory of ssca_mfma_scratch_bytes(N, Np, batch) bytes for the 16-bit copies of x and the DFT weights,
@@ -85,8 +82,9 @@ __host__ __device__ inline MlpLayout mlp_layout(int Np) {
   L.total = L.b3 + Np;
   return L;
 }
-// seg: [nsig][16][Np][1024] segment SSCAs -> feat [nsig][2 Np] (centred PSD, ACP).
-hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t stream);
+// seg: [nsig][16][Np][1024] segment SSCAs -> feat [nsig][2 Np] (PSD, centred over k if `centre`; ACP).
+hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t stream,
+                               bool centre = true);
 // S: [nsig][Np][N] -> labels [nsig][Np] (0/1), ratio [nsig][Np] (may be null).
 hipError_t launch_labels(const float2* S, int64_t N, int Np, int nsig, float* labels, float* ratio,
                          hipStream_t stream);
@@ -100,11 +98,11 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int 
                        float eps, hipStream_t stream);
 hipError_t launch_select(const float* sc, int Np, int nsig, float theta, unsigned char* mask, float* conf,
                          hipStream_t stream);
-// Selector inference of one signal in one kernel: standardise feat [2 Np], MLP, strip mask (device Np bytes),
-// confidence, fallback to every strip when the confidence is below conf_min (fell = 1), and the ChanSel the
-// SSCA kernels read.
+// Selector inference of one signal: centre the PSD part of the raw feat [2 Np] and standardise, MLP (activations in h: 2 * 256 + Np floats of
+// device scratch), strip mask (device Np bytes), confidence, fallback to every strip when the confidence is
+// below conf_min (fell = 1), and the ChanSel the SSCA kernels read.
 hipError_t launch_select_infer(const float* feat, const float* mu, const float* sigma, const float* params, int Np,
-                               float theta, float conf_min, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
-                               hipStream_t stream);
+                               float theta, float conf_min, float* h, unsigned char* mask, float* conf, int* fell,
+                               ChanSel* sel, hipStream_t stream);
 
 }  // namespace scd

@@ -31,16 +31,7 @@ constexpr int kSeqStride = kSeq + kSeq / 16;  // one float2 of padding per 16 el
 constexpr int kHalfSeqs = 32;         // 8 channels x 4 residues per LDS exchange
 constexpr int kXchgFloats = kHalfSeqs * kSeqStride;
 constexpr int kP2Threads = 256;
-
-// Complex window of channel subset c: hc[c][j] = w[j] * omega_Np^{(c j) mod Np}.
-__global__ void ssca_hc_kernel(const float* __restrict__ win, const float2* __restrict__ tabs,
-                               float2* __restrict__ hc, int Np, int S) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < S * Np) {
-    const int c = e / Np, j = e % Np;
-    hc[e] = cscale(tabs[kTabRoots + ((c * j) & (Np - 1))], win[j]);
-  }
-}
+constexpr int kPairMinBlocks = 256;   // paired Stage-1 grids at least this large (one block per CU)
 
 // omega_N^a for 0 <= a < N from the two-level table: omega_N^{a mod 1024} * omega_1024^{(a / 1024) * 1024 / M2}.
 __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
@@ -72,7 +63,7 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 // LDS table.
 template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR>
 __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) void ssca_pass1_fp32(
-    const float2* __restrict__ x, int N, int M2, int m2shift, const float2* __restrict__ hcg,
+    const float2* __restrict__ x, int N, int M2, int m2shift, const float* __restrict__ win,
     const float2* __restrict__ tabs, float2* __restrict__ T, int64_t xbs, int64_t tbs,
     const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
@@ -104,7 +95,6 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
   const float2* rlo = tabs + kTabRotLo;
-  const float2* hc = hcg + cg * NP;
   const auto xr = make_rsrc(x, N * 8);
   const int hishift = 10 - m2shift;
 
@@ -115,9 +105,12 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     for (int i = tid; i < NP; i += NTH) rt[i] = tabs[kTabRoots + i];
 
   const int j0 = tid & 15, fi = tid >> 4;
-  float2 hl[NT];
+  float2 hl[NT];  // the subset's complex window w[j] omega_Np^{(cg j) mod Np} at j = j0 + 16 j1
 #pragma unroll
-  for (int j1 = 0; j1 < NT; ++j1) hl[j1] = hc[j0 + 16 * j1];
+  for (int j1 = 0; j1 < NT; ++j1) {
+    const int j = j0 + 16 * j1;
+    hl[j1] = cscale(tabs[kTabRoots + ((cg * j) & (NP - 1))], win[j]);
+  }
   const float2 w32 = tw_g[32 * j0];  // omega_32^{j0}
   // When Np divides M2 the down-conversion factor omega_Np^{(c + S k') m2} does not depend on the frame. Its
   // k'-dependent part omega_16^{k' m2} is a cyclic shift of the 16-point DFT's input by m2, applied by storing
@@ -345,24 +338,32 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
 }
 
 template <int NP>
-hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs, float2* hc,
+hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs,
                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
-  constexpr int S = NP / 16;
-  constexpr bool PAIR = NP >= 32;  // subsets c and c + Np/32 share one workgroup
-  const int units = PAIR ? sel.npair : sel.nsub;
-  if (units <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ssca_hc_kernel, dim3((S * NP + 255) / 256), dim3(256), 0, s, win, tabs, hc, NP, S);
-  dim3 grid(M2 * units, batch);
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, grid, dim3((PAIR ? 2 : 1) * kP1Threads), 0, s, x, N, M2, m2shift, hc, tabs, T, xbs,
+  if (sel.nsub <= 0) return hipSuccess;
+  // Subset pairs halve the x traffic and the fold work per strip; they are used when the paired grid still
+  // gives every CU a workgroup (otherwise, e.g. for short segments, twice as many single-subset workgroups
+  // finish sooner).
+  auto go = [&](auto kern, bool pair) {
+    dim3 grid(M2 * (pair ? sel.npair : sel.nsub), batch);
+    hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, N, M2, m2shift, win, tabs, T, xbs,
                        tbs, sel.dev);
   };
-  if (M2 % NP == 0) {
-    if (sel.dev) go(ssca_pass1_fp32<NP, true, true, PAIR>);
-    else go(ssca_pass1_fp32<NP, true, false, PAIR>);
+  auto launch = [&](auto pair_tag) {
+    constexpr bool PAIR = decltype(pair_tag)::value;
+    if (M2 % NP == 0) {
+      if (sel.dev) go(ssca_pass1_fp32<NP, true, true, PAIR>, PAIR);
+      else go(ssca_pass1_fp32<NP, true, false, PAIR>, PAIR);
+    } else {
+      if (sel.dev) go(ssca_pass1_fp32<NP, false, true, PAIR>, PAIR);
+      else go(ssca_pass1_fp32<NP, false, false, PAIR>, PAIR);
+    }
+  };
+  if constexpr (NP >= 32) {
+    if (static_cast<int64_t>(M2) * sel.npair * batch >= kPairMinBlocks) launch(std::true_type{});
+    else launch(std::false_type{});
   } else {
-    if (sel.dev) go(ssca_pass1_fp32<NP, false, true, PAIR>);
-    else go(ssca_pass1_fp32<NP, false, false, PAIR>);
+    launch(std::false_type{});
   }
   return hipGetLastError();
 }
@@ -381,17 +382,17 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int ba
 
 }  // namespace
 
-hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* hc,
+hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs,
                                   float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
-    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
-    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
-    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
-    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, hc, T, batch, xbs, tbs, sel, s);
+    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
+    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
+    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
+    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
+    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
     default: return hipErrorInvalidValue;
   }
 }
