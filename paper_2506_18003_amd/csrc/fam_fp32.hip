@@ -60,21 +60,23 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
                                                              const float2* __restrict__ tabs,
                                                              float2* __restrict__ out, int64_t xtbs,
                                                              int64_t obs) {
+  constexpr int TWN = P < 16 ? 16 : P;  // omega_P^e (at least the 16 roots a radix-16 stage may index)
   __shared__ float2 buf[kLT * P];
-  __shared__ float2 tw[1024];
+  __shared__ float2 tw[TWN];
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * kLT;
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
   out += blockIdx.z * obs;
-  for (int i = tid; i < 1024; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < TWN; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i * (1024 / TWN)];
   __syncthreads();
   const float2* rk = xt + static_cast<int64_t>(k) * P;
   const float2* rl = xt + static_cast<int64_t>(l0) * P;
   float2* dst = out + (static_cast<int64_t>(k) * Np + l0) * P;
   auto ld = [&](int b, int m) { return cmulc(rk[m], rl[b * P + m]); };
-  auto st = [&](int b, int m, float2 v) { dst[b * P + m] = v; };
-  lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>>(buf, tw, tid, ld, st);
+  // The output is written once and never read back here: stream it past the caches.
+  auto st = [&](int b, int m, float2 v) { st1_nt(dst + b * P + m, v); };
+  lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
 }
 
 template <int NP>

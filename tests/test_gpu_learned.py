@@ -154,6 +154,37 @@ def test_learned_ssca_selected_strips_equal_full(dev, prec):
     assert torch.equal(out[nk], sentinel[nk])
 
 
+def test_learned_ssca_no_strip_selected(dev):
+    """All scores below theta and a confident selector: nothing is computed and out is left untouched (the
+    Stage 1 and Stage 2 grids exit on the device-side selection)."""
+    N, Np = 1 << 15, 64
+    x = gpu(sg.qpsk(N, 0.1, 8, 5.0, sg.rng_for(84, 0)), dev)
+    sel = _fixed_selector(Np, np.zeros(Np, bool), dev)
+    sentinel = torch.full((Np, N), complex(3.0, 1.0), dtype=torch.complex64, device=dev)
+    out, mask, fb = SEL.ssca_learned(x, sel, out=sentinel.clone())
+    assert not fb and int(mask.sum()) == 0
+    assert torch.equal(out, sentinel)
+
+
+@pytest.mark.parametrize("Np,strips", [(64, [2]), (64, [5, 9]), (16, [0, 7, 15]), (128, [1, 127])])
+def test_learned_ssca_partial_selections(dev, Np, strips):
+    """Selections that leave one subset of a pair (or, at Np = 16, of the single-subset kernel) unused: the
+    chosen strips equal the full SSCA and every other row keeps its previous content."""
+    N = 1 << 16
+    x = gpu(sg.bpsk(N, 0.07, 6, 4.0, sg.rng_for(85, Np)), dev)
+    keep = np.zeros(Np, bool)
+    keep[strips] = True
+    sel = _fixed_selector(Np, keep, dev)
+    sentinel = torch.full((Np, N), complex(-2.0, 5.0), dtype=torch.complex64, device=dev)
+    out, mask, fb = SEL.ssca_learned(x, sel, out=sentinel.clone())
+    assert not fb and np.array_equal(mask.cpu().numpy().astype(bool), keep)
+    full = scd.ssca(x, Np)
+    k = torch.from_numpy(np.nonzero(keep)[0]).to(dev)
+    nk = torch.from_numpy(np.nonzero(~keep)[0]).to(dev)
+    assert torch.equal(out[k], full[k])
+    assert torch.equal(out[nk], sentinel[nk])
+
+
 def test_learned_ssca_fallback_forced(dev):
     N, Np = 1 << 14, 32
     x = gpu(sg.bpsk(N, 0.1, 8, 5.0, sg.rng_for(83, 0)), dev)
