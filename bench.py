@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fam", action="store_true", help="skip the FAM batch measurement")
+    ap.add_argument("--mix-signals", type=int, default=8,
+                    help="held-out selector-recipe signals for the learned form's mixed-workload line (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB read + 256 MiB write elementwise kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -172,6 +174,41 @@ def main():
         learned_info = dict(ms_per_step=lms, strips=int(m.sum()), fell_back=bool(fb), recall_vs_full=recall,
                             active_strips=int(labels.sum()), out=lout.cpu().numpy(), mask=m)
         del full
+        # The same comparison over held-out signals of the selector's own recipe (test-split seeds, every
+        # modulation and noise, SNR in [-10, 15] dB) at N = 2^20: what the selection buys when not every strip
+        # carries a cyclic feature.
+        mix_full, mix_learned, mix_strips, mix_tp, mix_pos, mix_fb = [], [], 0, 0, 0, 0
+        for i in range(args.mix_signals):
+            xm = torch.from_numpy(W.selector_signal(i, "test", emin=20, emax=20)[1].astype(np.complex64)).to(dev)
+            for _ in range(2):
+                scd.ssca_stage1(xm, Np, inter, win=win)
+                scd.ssca_stage2(inter, N, Np, out)
+                SEL.ssca_learned(xm, sel, win=win, out=lout, want_fallback=False)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            for _ in range(5):
+                scd.ssca_stage1(xm, Np, inter, win=win)
+                scd.ssca_stage2(inter, N, Np, out)
+            e[1].record(stream)
+            for _ in range(5):
+                SEL.ssca_learned(xm, sel, win=win, out=lout, want_fallback=False)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            mix_full.append(e[0].elapsed_time(e[1]) / 5)
+            mix_learned.append(e[1].elapsed_time(e[2]) / 5)
+            _, mm, fbm = SEL.ssca_learned(xm, sel, win=win, out=lout)
+            mm = mm.cpu().numpy().astype(bool)
+            lab = SEL.strip_labels(out)[0].cpu().numpy()[0] > 0.5
+            mix_strips += int(mm.sum())
+            mix_tp += int((mm & lab).sum())
+            mix_pos += int(lab.sum())
+            mix_fb += int(bool(fbm))
+        if args.mix_signals:
+            learned_info["mix"] = dict(
+                signals=args.mix_signals, full_ms=float(np.mean(mix_full)), learned_ms=float(np.mean(mix_learned)),
+                speedup_vs_fp32=float(np.mean(mix_full) / np.mean(mix_learned)),
+                strip_fraction=mix_strips / (args.mix_signals * Np), recall=mix_tp / max(1, mix_pos),
+                active_fraction=mix_pos / (args.mix_signals * Np), fallbacks=mix_fb)
     for form in forms:
         for _ in range(args.warmup):
             scd.ssca_stage1(x, Np, inter, win=win, precision=form)
@@ -321,6 +358,10 @@ def main():
             "fell_back": li["fell_back"], "active_strips": li["active_strips"],
             "recall_vs_full": li["recall_vs_full"], "max_err_vs_oracle": errs.get("learned"),
             "note": "whole scd_ssca_learned call: features, fused MLP + selection kernel, selected strips (asynchronous)"}
+        if "mix" in li:
+            line["forms"]["learned"]["mix"] = dict(
+                workload=f"{li['mix']['signals']} held-out signals of the selector recipe at N=2^20, Np={Np}",
+                **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in li["mix"].items()})
     print(json.dumps(line), flush=True)
 
 
