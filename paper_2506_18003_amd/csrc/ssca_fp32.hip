@@ -38,11 +38,9 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
   return cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
 }
 
-// Stage 1. The flattened block index is mapped so that each of the 8 XCDs (which receive blocks round-robin)
-// walks a contiguous range of m2, all channel subsets of one m2 next to each other: the frames of
-// neighbouring m2 overlap in all but one sample, so an XCD's share of x stays in its L2. With a selection in
-// device memory the grid covers every subset and the workgroups past the selected count exit at once, so
-// the host never needs to know the selection. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
+// Stage 1. Blocks run m2 fastest (see block_to_m2_unit for how that spreads x over the XCDs' L2 caches). With
+// a selection in device memory the grid covers every subset and the workgroups past the selected count exit
+// at once, so the host never needs to know the selection. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
 // a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2, with 256 threads per subset;
 // thread t of a subset owns frames m1 = t + 256 f (f < 4).
 //

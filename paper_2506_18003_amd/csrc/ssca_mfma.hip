@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 5, lc = lane & 31;
   int m2, u;
-  block_to_m2_unit(M2, m2shift, m2, u);
+  block_to_m2_unit_xcd(M2, m2shift, m2, u);
   if (SEL && u >= sel->nsub) return;
   const int c = SEL ? sel->sub[u] : u;
   x += blockIdx.y * xbs;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
   const int lane = tid & 63, wave = tid >> 6, g = lane >> 5, lc = lane & 31;
   const int half = tid >> 8, t = tid & 255;
   int m2, u;
-  block_to_m2_unit(M2, m2shift, m2, u);
+  block_to_m2_unit_xcd(M2, m2shift, m2, u);
   if (SEL && u >= sel->npair) return;
   const int cg = SEL ? sel->pair[u] : u;
   x += blockIdx.y * xbs;
