@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
       const int k = chalf + S * (8 * h + (b >> 2));
       const int m1p = (b & 3) + 4 * (m & 15) + 64 * (m >> 4);
       if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
-        st1_nt(T + ((k * (kM1 / 16) + (m1p >> 4)) * M2 + m2) * 16 + (m1p & 15), cmul(v, rot[m1p]));
+        T[((k * (kM1 / 16) + (m1p >> 4)) * M2 + m2) * 16 + (m1p & 15)] = cmul(v, rot[m1p]);
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);
