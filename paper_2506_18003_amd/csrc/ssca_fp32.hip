@@ -1,19 +1,20 @@
 // Plain FP32 SSCA (Sec. II-C, Eq. (6)-(7)) computed as the paper's SSCA_2DFFT (Sec. III-B, Eq. (10)-(16)),
 // with N = M1 * M2, M1 = 1024 and M2 = N / 1024.
 //
-// Pass 1 (one workgroup per (m2, channel subset)): generates the channel-data product X_g only where Stage 1
-// needs it. For every m1 it forms the centred, windowed frame n = m1*M2 + m2 (Eq. (3), L = 1), evaluates the
-// 16 channels k = c + S*k' (S = Np/16) of the subset with a pruned DFT, applies the down-conversion factor
-// omega_Np^{(k n) mod Np} and the conjugate sample conj(x[n]) (Eq. (6)), and keeps X_g(m1, m2, k) in
-// registers. It then takes the M1-point DFT over m1 (Stage 1), multiplies by the rotation factor
+// Stage 1 (one workgroup per (m2, channel subset or subset pair)): generates the channel-data product X_g
+// only where Stage 1 needs it. For every m1 it forms the centred, windowed frame n = m1*M2 + m2 (Eq. (3),
+// L = 1), evaluates the 16 channels k = c + S*k' (S = Np/16) of each subset with a pruned DFT, applies the
+// down-conversion factor omega_Np^{(k n) mod Np} and the conjugate sample conj(x[n]) (Eq. (6)), and keeps
+// X_g(m1, m2, k) in registers. It then takes the M1-point DFT over m1, multiplies by the rotation factor
 // omega_N^{m2 m1'} and stores the result to HBM in a blocked layout T[k][m1'/16][m2][m1' % 16], so both this
-// store and pass 2's load move whole 128-byte runs.
+// store and Stage 2's load move whole 128-byte runs.
 //
-// Pass 2 (one workgroup per (16 consecutive m1', k)): Stage 2, the M2-point DFT over m2 of the 16 rows,
-// stored at S[k][q] with q = m1' + M1*m2' (16 consecutive q per run).
+// Stage 2 (one workgroup per (16 consecutive m1', k)): the M2-point DFT over m2 of the 16 rows, stored at
+// S[k][q] with q = m1' + M1*m2' (16 consecutive q per run).
 //
-// Pruned channel-subset DFT: with j = j0 + 16*j1 (j0 < 16, j1 < S) and k = c + S*k',
-//   sum_j v[j] omega_Np^{k j} = sum_{j0} omega_16^{k' j0} [ sum_{j1} (w[j] omega_Np^{c j}) x[n-d+j] ],
+// Pruned channel-subset DFT: with the subset's complex window hc[j] = w[j] omega_Np^{(c j) mod Np},
+// j = j0 + 16*j1 (j0 < 16, j1 < S) and k = c + S*k',
+//   sum_j w[j] x[n-d+j] omega_Np^{k j} = sum_{j0} omega_16^{k' j0} [ sum_{j1} hc[j] x[n-d+j] ],
 // so each subset costs one complex-windowed fold of the frame to 16 points plus a 16-point DFT.
 #include <type_traits>
 
@@ -40,9 +41,9 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 
 // Stage 1. Blocks run m2 fastest (see block_to_m2_unit for how that spreads x over the XCDs' L2 caches). With
 // a selection in device memory the grid covers every subset and the workgroups past the selected count exit
-// at once, so the host never needs to know the selection. A workgroup computes one channel subset (PAIR false: strips k = c mod Np/16) or
-// a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2, with 256 threads per subset;
-// thread t of a subset owns frames m1 = t + 256 f (f < 4).
+// at once, so the host never needs to know the selection. A workgroup computes one channel subset (PAIR
+// false: strips k = c mod Np/16) or a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2,
+// with 256 threads per subset; thread t of a subset owns frames m1 = t + 256 f (f < 4).
 //
 // Fold: for each group f of 256 frames, lane (frame i, residue j0 = tid % 16) forms
 //   A = sum_{j1 < Np/16} hc[j0 + 16 j1] x[n - d + j0 + 16 j1]
