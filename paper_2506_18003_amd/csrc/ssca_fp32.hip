@@ -49,12 +49,13 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 //   A = sum_{j1 < Np/16} hc[j0 + 16 j1] x[n - d + j0 + 16 j1]
 // over the rounds that cover the group. A wave's loads cover 4 frames x 16 consecutive samples (whole
 // 128-byte lines, straight from L2, with loads for the next rounds kept in flight in a register ring), and
-// only 16 folded values per frame pass through LDS, where thread t picks up frame t's row. In a pair the
-// same loads serve both subsets: with j = j0 + 32 m + 16 e, the 32-channel subset c (strips c mod Np/32) is the
-// 32-point DFT of u[j0 + 16 e] = sum_m hc[j0 + 32 m + 16 e] x[...]; its even outputs are the 16-point DFT of
-// u[j0] + u[j0 + 16] (subset c) and its odd outputs that of (u[j0] - u[j0 + 16]) omega_32^{j0}
-// (subset c + Np/32). Each thread then takes the 16-point DFT and multiplies by conj(x[n]) (and, when Np does
-// not divide M2, by the per-frame down-conversion factor), keeping the 16 channel values in registers.
+// only 16 folded values per frame (and the frame's own sample x[n]) pass through LDS, where thread t picks up
+// frame t's row. In a pair the same loads serve both subsets: with j = j0 + 32 m + 16 e, the 32-channel
+// subset c (strips c mod Np/32) is the 32-point DFT of u[j0 + 16 e] = sum_m hc[j0 + 32 m + 16 e] x[...]; its
+// even outputs are the 16-point DFT of u[j0] + u[j0 + 16] (subset c) and its odd outputs that of
+// (u[j0] - u[j0 + 16]) omega_32^{j0} (subset c + Np/32). Each thread then takes the 16-point DFT and
+// multiplies by conj(x[n]) (and, when Np does not divide M2, by the per-frame down-conversion factor),
+// keeping the 16 channel values in registers.
 //
 // The M1 = 1024-point DFT over m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle
 // omega_1024^{t r}, and a 256-point DFT over t in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its
@@ -135,6 +136,9 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     for (int r = 0; r < RPG; ++r) {
       const int g = RPG * f + r;
       const int row = (FPR * r + fi) * kURow + jcol;
+      // Tap j = D of frame m1 is the frame's own sample x[n] (n - D + j = n): the lane of residue D mod 16
+      // holds it as tap D / 16 and parks it in the row's padding slot for the channel-data product.
+      if (j0 == (D & 15)) ub[(FPR * r + fi) * kURow + 16] = ring[g % PF][D >> 4];
       if constexpr (PAIR) {
         float2 ea = cmul(hl[0], ring[g % PF][0]);
         float2 eb = cmul(hl[1], ring[g % PF][1]);
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     for (int j = 0; j < 16; ++j) u[j] = ub[half * kUBuf + t * kURow + j];
     dft16(u);
     const int n = (t + 256 * f) * M2 + m2;
-    const float2 xn = load_c64(xr, n);
+    const float2 xn = ub[t * kURow + 16];
     const float2 xp = cmulc(xn, cphase);  // x[n] conj(omega_Np^{c m2})
 #pragma unroll
     for (int kp = 0; kp < 16; ++kp) {
