@@ -6,7 +6,8 @@
 //   X_T is at most 256 x 1024 complex (2 MiB) and stays in L2.
 // fam_pair: for channel k and a tile of 16 channels l, forms z[p] = X_T[p][k] conj(X_T[p][l]) (the conjugate
 //   multiplication of Eq. (5)) while loading, takes the P-point DFT of the 16 products in LDS and stores
-//   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic).
+//   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic). Row k, which all
+//   16 products share, is staged in LDS once, so each thread's global loads are only its rows l.
 #include <type_traits>
 
 #include "scd_device.h"
@@ -63,14 +64,15 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
   constexpr int TWN = P < 16 ? 16 : P;  // omega_P^e (at least the 16 roots a radix-16 stage may index)
   __shared__ float2 buf[kLT * P];
   __shared__ float2 tw[TWN];
+  __shared__ float2 rk[P];  // row k of X_T
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * kLT;
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
   out += blockIdx.z * obs;
   for (int i = tid; i < TWN; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i * (1024 / TWN)];
+  for (int i = tid; i < P; i += kPairThreads) rk[i] = xt[static_cast<int64_t>(k) * P + i];
   __syncthreads();
-  const float2* rk = xt + static_cast<int64_t>(k) * P;
   const float2* rl = xt + static_cast<int64_t>(l0) * P;
   float2* dst = out + (static_cast<int64_t>(k) * Np + l0) * P;
   auto ld = [&](int b, int m) { return cmulc(rk[m], rl[b * P + m]); };
