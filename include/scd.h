@@ -223,6 +223,29 @@ int scd_select(const float* scores, int Np, int batch, float theta, unsigned cha
 int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
                      unsigned char* mask, int* fell_back, const scd_opts* opts);
 
+/* One signal of scd_ssca_batch. */
+typedef struct scd_ssca_item {
+  const float* x;               /* device, N complex values                                                */
+  int64_t N;                    /* as scd_ssca; a power of two in [2^14, 2^20] when a selector is given     */
+  int Np;                       /* as scd_ssca                                                             */
+  const float* win;             /* device, Np floats                                                       */
+  float* out;                   /* device, Np*N complex values, [Np][N]                                    */
+  const scd_selector* selector; /* NULL: every strip; otherwise only the strips this selector picks       */
+  unsigned char* mask;          /* with a selector: device Np bytes, written as by scd_ssca_learned; else
+                                   unused                                                                  */
+} scd_ssca_item;
+
+/* SSCA of n signals of any lengths and channel counts, enqueued in item order on one stream (a library form
+ * for mixed workloads; the paper estimates one signal at a time). An item without a selector runs as
+ * scd_ssca_ex; an item with one runs as scd_ssca_learned with fell_back NULL, so the call never waits for the
+ * GPU. Every item uses opts' precision, stream and workspace. opts->batch must be 0 or 1 and both strides 0:
+ * each item is one signal. A caller workspace must hold the largest item's intermediate; the library-owned one
+ * grows to it, waiting for the device once when it grows. The call stops at the first item that fails and
+ * returns that item's error code, with the item's index in scd_last_error; the items before it stay enqueued.
+ * Errors: SCD_ERR_NULL (items NULL with n > 0), SCD_ERR_SIZE (n < 0 or opts->batch > 1), SCD_ERR_UNSUPPORTED
+ * (nonzero strides), and those of scd_ssca_ex and scd_ssca_learned. */
+int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts);
+
 /* Bytes of workspace scd_ssca_ex needs for `batch` signals (0 when N == 1024). Errors: SCD_ERR_NULL,
  * SCD_ERR_SIZE. */
 int scd_ssca_workspace_size(int64_t N, int Np, int batch, size_t* bytes);

@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_stage1", "ssca_stage2", "fam", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -93,6 +93,47 @@ def ssca(x, Np: int, win=None, precision="fp32", out=None, workspace=None):
     with torch.cuda.device(x.device):
         _lib.check(_lib.lib().scd_ssca_ex(x.data_ptr(), N, Np, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
     return out
+
+
+def ssca_batch(items, precision="fp32", workspace=None):
+    """SSCA of several signals of any lengths and channel counts in one call; see scd_ssca_batch.
+
+    `items` is a list of dicts with keys x (complex64 CUDA tensor [N]) and Np, and optionally win, out and
+    selector (a selector.Selector: only the strips it picks are computed, the other rows of out stay zero).
+    Returns one (out, mask) pair per item; mask is the uint8 [Np] selection, None for items without a selector.
+    """
+    torch = _torch()
+    if not items:
+        return []
+    dev = items[0]["x"].device
+    arr = (_lib.ScdSscaItem * len(items))()
+    keep, res = [], []
+    for i, it in enumerate(items):
+        x, Np = it["x"], int(it["Np"])
+        _check_x(x)
+        if x.dim() != 1 or x.device != dev:
+            raise ValueError("every item's x must be one signal [N] on the same device")
+        N = x.shape[-1]
+        w = _window(it.get("win"), Np, dev)
+        sel = it.get("selector")
+        out = it.get("out")
+        if out is None:
+            out = (torch.zeros if sel is not None else torch.empty)(Np, N, dtype=torch.complex64, device=dev)
+        elif tuple(out.shape) != (Np, N) or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"item {i}: out must be a contiguous complex64 tensor of shape {(Np, N)}")
+        mask = torch.empty(Np, dtype=torch.uint8, device=dev) if sel is not None else None
+        arr[i].x, arr[i].N, arr[i].Np, arr[i].win, arr[i].out = x.data_ptr(), N, Np, w.data_ptr(), out.data_ptr()
+        if sel is not None:
+            cs = sel.c_struct()
+            keep.append(cs)
+            arr[i].selector = ctypes.pointer(cs)
+            arr[i].mask = mask.data_ptr()
+        keep.append(w)
+        res.append((out, mask))
+    o = _opts(items[0]["x"], precision, 1, 0, 0, workspace)
+    with torch.cuda.device(dev):
+        _lib.check(_lib.lib().scd_ssca_batch(arr, len(items), ctypes.byref(o)))
+    return res
 
 
 def ssca_stage1(x, Np: int, inter, win=None, precision="fp32"):

@@ -55,6 +55,18 @@ class ScdSelector(ctypes.Structure):
     ]
 
 
+class ScdSscaItem(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p),
+        ("N", ctypes.c_int64),
+        ("Np", ctypes.c_int),
+        ("win", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("selector", ctypes.POINTER(ScdSelector)),
+        ("mask", ctypes.c_void_p),
+    ]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -81,6 +93,7 @@ _SIGS = {
     "scd_select": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float, _P, _P, _P]),
     "scd_ssca_learned": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ScdOpts)]),
+    "scd_ssca_batch": (ctypes.c_int, [ctypes.POINTER(ScdSscaItem), ctypes.c_int, ctypes.POINTER(ScdOpts)]),
     "scd_set_stream": (ctypes.c_int, [_P]),
     "scd_last_error": (ctypes.c_char_p, []),
     "scd_version": (ctypes.c_int, []),

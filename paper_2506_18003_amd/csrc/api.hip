@@ -560,6 +560,26 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
   return SCD_OK;
 }
 
+int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts) {
+  if (n < 0) return fail(SCD_ERR_SIZE, "n must be at least 0");
+  if (n > 0 && !items) return fail(SCD_ERR_NULL, "NULL argument");
+  if (opts && opts->batch > 1) return fail(SCD_ERR_SIZE, "each item is one signal: opts->batch must be 0 or 1");
+  if (opts && (opts->x_stride != 0 || opts->out_stride != 0))
+    return fail(SCD_ERR_UNSUPPORTED, "strides do not apply to scd_ssca_batch items");
+  // Items share the stream, so the library's intermediate and selector scratch are reused in stream order.
+  for (int i = 0; i < n; ++i) {
+    const scd_ssca_item& it = items[i];
+    const int rc = it.selector
+                       ? scd_ssca_learned(it.x, it.N, it.Np, it.win, it.selector, it.out, it.mask, nullptr, opts)
+                       : scd_ssca_ex(it.x, it.N, it.Np, it.win, it.out, opts);
+    if (rc != SCD_OK) {
+      const std::string why = g_err;
+      return fail(rc, "item %d: %s", i, why.c_str());
+    }
+  }
+  return SCD_OK;
+}
+
 void scd_shutdown(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_dev.empty()) return;

@@ -133,3 +133,24 @@ def test_learned_entry_errors(L):
     assert L.scd_ssca_learned(_fake(X), 1 << 16, 64, _fake(W), ctypes.byref(sel), _fake(O), _fake(O + 8),
                               None, None) == _lib.SCD_ERR_MODEL
     assert L.scd_adam_step(0, _fake(X), _fake(W), _fake(O), _fake(O), 1, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.SCD_ERR_SIZE
+
+
+def test_ssca_batch_errors(L):
+    o = _lib.ScdOpts()
+    assert L.scd_ssca_batch(None, -1, None) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_batch(None, 1, None) == _lib.SCD_ERR_NULL
+    assert L.scd_ssca_batch(None, 0, None) == _lib.SCD_OK
+    items = (_lib.ScdSscaItem * 2)()
+    o.batch = 2
+    assert L.scd_ssca_batch(items, 2, ctypes.byref(o)) == _lib.SCD_ERR_SIZE
+    o.batch, o.x_stride = 1, 5
+    assert L.scd_ssca_batch(items, 2, ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
+    # The first failing item stops the call and is named in the message.
+    items[0].x, items[0].N, items[0].Np, items[0].win, items[0].out = _fake(X), 3000, 64, _fake(W), _fake(O)
+    assert L.scd_ssca_batch(items, 2, None) == _lib.SCD_ERR_SIZE
+    assert L.scd_last_error().startswith(b"item 0:")
+    sel = _lib.ScdSelector()
+    sel.Np = 64
+    items[0].N, items[0].selector, items[0].mask = 1 << 16, ctypes.pointer(sel), _fake(O + 8)
+    assert L.scd_ssca_batch(items, 1, None) == _lib.SCD_ERR_MODEL
+    assert L.scd_last_error().startswith(b"item 0:")
