@@ -306,6 +306,25 @@ def main():
                         fp["win"].astype(np.float32).astype(np.float64))
             fam_line["max_err_vs_oracle_signal0"] = float(np.abs(fout[0].cpu().numpy() - ref).max() / np.abs(ref).max())
         del fout
+        # The paper's output form (|S|^2 over |q_c| < P/4, scd_fam_power_ex): same kernels, a quarter of the
+        # output bytes.
+        pout = torch.empty(fB, fNp, fNp, fP // 2, dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            scd.fam_power(fx, fNp, fL, fP, win=fw, out=pout)
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            fev[i][0].record(stream)
+            scd.fam_power(fx, fNp, fL, fP, win=fw, out=pout)
+            fev[i][1].record(stream)
+        torch.cuda.synchronize()
+        pms = float(np.mean([e[0].elapsed_time(e[1]) for e in fev]))
+        pbytes = 8 * fB * fP * fL + 2 * 8 * fB * fNp * fP + 4 * fB * fNp * fNp * (fP // 2)
+        fam_line["power_form"] = {"ms_per_batch": round(pms, 5),
+                                  "pts_per_s": round(fB * fNp * fNp * (fP // 2) / (pms * 1e-3), 1),
+                                  "speedup_vs_complex": round(fms / pms, 3),
+                                  "achieved_GBs": round(pbytes / (pms * 1e-3) / 1e9, 1),
+                                  "algorithmic_bytes": pbytes}
+        del pout
 
     cpu = None
     errs = {}

@@ -147,6 +147,15 @@ int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out);
 /* scd_fam with options (batch, strides, stream, workspace for X_T). Only SCD_FP32 is supported. */
 int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
 
+/* scd_fam_power_ex - the output the paper's FAM keeps (Alg. 1: |S|^2 of the second FFT over its central half,
+ * the bins with |q_c| < P/4), written by the FAM kernel itself instead of the complex grid:
+ *   out[k][l][j] = |S[k][l][q]|^2, q = j for j < P/4 and q = j + P/2 for j >= P/4 (j < P/2),
+ * each power rounded as re*re + im*im with every operation rounded to FP32 (no fused multiply-add).
+ *   out  device, Np*Np*(P/2) floats per signal, row-major [Np][Np][P/2]; opts->out_stride counts floats.
+ * Arguments, sizes, options and errors otherwise as scd_fam_ex. The output is a quarter of the complex grid's
+ * bytes, which dominate FAM's HBM traffic. */
+int scd_fam_power_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
+
 /* ---------------------------------------------------------------------------------------------------------
  * Learned strip selection. The paper has no learned component (its glossary only names the averaged cyclic
  * periodogram and the PSD, and its conclusion points at a machine-learning back-end); the definitions below

@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -188,6 +188,32 @@ def fam(x, Np: int, L: int | None = None, P: int | None = None, win=None, out=No
     return out
 
 
+def fam_power(x, Np: int, L: int | None = None, P: int | None = None, win=None, out=None, workspace=None):
+    """The paper's FAM output, |S[k][l][q]|^2 over |q_c| < P/4 ([.., Np, Np, P/2] float32, bins in the order of
+    fam_paper_view), written by the FAM kernel itself; see scd_fam_power_ex."""
+    torch = _torch()
+    _check_x(x)
+    if L is None:
+        L = Np // 4
+    if P is None:
+        P = x.shape[-1] // L
+    if x.shape[-1] < P * L:
+        raise ValueError(f"x has {x.shape[-1]} samples, FAM needs P*L = {P * L}")
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, Np, P // 2) if x.dim() == 1 else (B, Np, Np, P // 2)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, "fp32", B, xs, Np * Np * (P // 2), workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_fam_power_ex(x.data_ptr(), Np, L, P, w.data_ptr(), out.data_ptr(),
+                                               ctypes.byref(o)))
+    return out
+
+
 def ssca_workspace_size(N: int, Np: int, batch: int = 1) -> int:
     v = ctypes.c_size_t()
     _lib.check(_lib.lib().scd_ssca_workspace_size(N, Np, batch, ctypes.byref(v)))
@@ -231,8 +257,10 @@ def fam_coords(Np: int, L: int, P: int):
 
 def fam_paper_view(S):
     """|S|^2 over the central half of the alpha-offset axis (|q_c| < P/4), natural order
-    [0..P/4-1, -P/4..-1]; the bins the paper's FFT2 stage keeps."""
+    [0..P/4-1, -P/4..-1]; the bins the paper's FFT2 stage keeps. A view of a complex grid already computed
+    (re^2 + im^2, each operation rounded to FP32, as fam_power's kernel computes it)."""
     torch = _torch()
     P = S.shape[-1]
     idx = torch.cat([torch.arange(0, P // 4), torch.arange(P - P // 4, P)]).to(S.device)
-    return S.index_select(-1, idx).abs().square()
+    T = S.index_select(-1, idx)
+    return T.real.square() + T.imag.square()

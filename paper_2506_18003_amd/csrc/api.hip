@@ -335,20 +335,26 @@ int scd_ssca_stage2_ex(const float* inter, int64_t N, int Np, float* out, const 
   return ssca_common(SscaPart::kStage2, inter, N, Np, nullptr, out, opts);
 }
 
-int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts) {
+}  // extern "C"
+
+namespace {
+
+// FAM of Eq. (3)-(5); `power` selects the |S|^2 form over |q_c| < P/4 (float output, P/2 bins per pair).
+int fam_common(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts,
+               bool power) {
   if (!x || !win || !out) return fail(SCD_ERR_NULL, "x, win and out must be non-NULL");
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
   if (!is_pow2(L) || L > Np) return fail(SCD_ERR_SIZE, "L = %d must be a power of two in [1, Np]", L);
   if (!is_pow2(P) || P < 4 || P > 1024) return fail(SCD_ERR_SIZE, "P = %d must be a power of two in [4, 1024]", P);
   if (static_cast<int64_t>(P) * L > (1 << 16)) return fail(SCD_ERR_SIZE, "P*L must be at most 2^16");
   const int64_t n = static_cast<int64_t>(P) * L;
-  const int64_t olen = static_cast<int64_t>(Np) * Np * P;
+  const int64_t olen = static_cast<int64_t>(Np) * Np * (power ? P / 2 : P);
   Resolved r;
   int rc = resolve(opts, n, olen, &r);
   if (rc) return rc;
   if (r.precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "FAM is FP32 only");
   const size_t xb = span_bytes(r.batch, r.xs, n);
-  const size_t ob = span_bytes(r.batch, r.os, olen);
+  const size_t ob = span_bytes(r.batch, r.os, olen) / (power ? 2 : 1);  // float elements in the power form
   const size_t wb = 4u * static_cast<size_t>(Np);
   if (overlaps(out, ob, x, xb) || overlaps(out, ob, win, wb)) return fail(SCD_ERR_ALIAS, "out overlaps x or win");
   const size_t per = 8u * static_cast<size_t>(Np) * static_cast<size_t>(P);
@@ -373,14 +379,26 @@ int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* ou
   if (work) chunk = static_cast<int>(std::min<size_t>(r.batch, r.work_bytes / per));
   else if ((rc = get_work(st, per * r.batch, &work))) return rc;
   const float2* xc = reinterpret_cast<const float2*>(x);
-  float2* oc = reinterpret_cast<float2*>(out);
   for (int b0 = 0; b0 < r.batch; b0 += chunk) {
     const int nb = std::min(chunk, r.batch - b0);
-    hipError_t e = scd::launch_fam_fp32(xc + b0 * r.xs, Np, L, P, win, tabs, static_cast<float2*>(work),
-                                        oc + b0 * r.os, nb, r.xs, r.os, r.stream);
+    void* oc = power ? static_cast<void*>(out + b0 * r.os) : static_cast<void*>(reinterpret_cast<float2*>(out) + b0 * r.os);
+    hipError_t e = scd::launch_fam_fp32(xc + b0 * r.xs, Np, L, P, win, tabs, static_cast<float2*>(work), oc,
+                                        power, nb, r.xs, r.os, r.stream);
     if (e != hipSuccess) return hip_fail(e, "FAM launch");
   }
   return SCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts) {
+  return fam_common(x, Np, L, P, win, out, opts, false);
+}
+
+int scd_fam_power_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts) {
+  return fam_common(x, Np, L, P, win, out, opts, true);
 }
 
 int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out) {

@@ -7,7 +7,9 @@
 // fam_pair: for channel k and a tile of 16 channels l, forms z[p] = X_T[p][k] conj(X_T[p][l]) (the conjugate
 //   multiplication of Eq. (5)) while loading, takes the P-point DFT of the 16 products in LDS and stores
 //   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic). Row k, which all
-//   16 products share, is staged in LDS once, so each thread's global loads are only its rows l.
+//   16 products share, is staged in LDS once, so each thread's global loads are only its rows l. In the power
+//   form it stores only |S|^2 of the bins the paper keeps after its second FFT (Alg. 1), |q_c| < P/4, in the
+//   order q = 0..P/4-1, P-P/4..P-1: a quarter of the complex output's bytes.
 #include <type_traits>
 
 #include "scd_device.h"
@@ -56,10 +58,17 @@ __global__ __launch_bounds__(kChanThreads) void fam_chan_fp32(const float2* __re
   lds_fft<NP, F, kChanThreads, true, LdsLayout<NP, 1>>(buf, tw, tid, ld, st);
 }
 
-template <int P>
+// |v|^2 as re*re + im*im with each operation rounded to FP32 (no fused multiply-add), as the documented
+// power form is defined.
+__device__ __forceinline__ float power_rn(float2 v) {
+#pragma clang fp contract(off)
+  return v.x * v.x + v.y * v.y;
+}
+
+template <int P, bool POWER>
 __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __restrict__ xt, int Np,
                                                              const float2* __restrict__ tabs,
-                                                             float2* __restrict__ out, int64_t xtbs,
+                                                             void* __restrict__ out, int64_t xtbs,
                                                              int64_t obs) {
   constexpr int TWN = P < 16 ? 16 : P;  // omega_P^e (at least the 16 roots a radix-16 stage may index)
   __shared__ float2 buf[kLT * P];
@@ -69,16 +78,25 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
   const int l0 = blockIdx.x * kLT;
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
-  out += blockIdx.z * obs;
   for (int i = tid; i < TWN; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i * (1024 / TWN)];
   for (int i = tid; i < P; i += kPairThreads) rk[i] = xt[static_cast<int64_t>(k) * P + i];
   __syncthreads();
   const float2* rl = xt + static_cast<int64_t>(l0) * P;
-  float2* dst = out + (static_cast<int64_t>(k) * Np + l0) * P;
   auto ld = [&](int b, int m) { return cmulc(rk[m], rl[b * P + m]); };
   // The output is written once and never read back here: stream it past the caches.
-  auto st = [&](int b, int m, float2 v) { st1_nt(dst + b * P + m, v); };
-  lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
+  if constexpr (POWER) {
+    constexpr int H = P / 4;
+    float* dst = static_cast<float*>(out) + blockIdx.z * obs + (static_cast<int64_t>(k) * Np + l0) * (P / 2);
+    auto st = [&](int b, int m, float2 v) {
+      if (m < H || m >= P - H)
+        __builtin_nontemporal_store(power_rn(v), dst + b * (P / 2) + (m < H ? m : m - P / 2));
+    };
+    lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
+  } else {
+    float2* dst = static_cast<float2*>(out) + blockIdx.z * obs + (static_cast<int64_t>(k) * Np + l0) * P;
+    auto st = [&](int b, int m, float2 v) { st1_nt(dst + b * P + m, v); };
+    lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
+  }
 }
 
 template <int NP>
@@ -92,17 +110,22 @@ hipError_t chan(const float2* x, int L, int P, const float* win, const float2* t
 }
 
 template <int P>
-hipError_t pair(const float2* xt, int Np, const float2* tabs, float2* out, int batch, int64_t obs, hipStream_t s) {
+hipError_t pair(const float2* xt, int Np, const float2* tabs, void* out, bool power, int batch, int64_t obs,
+                hipStream_t s) {
   dim3 grid(Np / kLT, Np, batch);
-  hipLaunchKernelGGL(fam_pair_fp32<P>, grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
-                     static_cast<int64_t>(Np) * P, obs);
+  if (power)
+    hipLaunchKernelGGL((fam_pair_fp32<P, true>), grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
+                       static_cast<int64_t>(Np) * P, obs);
+  else
+    hipLaunchKernelGGL((fam_pair_fp32<P, false>), grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
+                       static_cast<int64_t>(Np) * P, obs);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs, float2* xt,
-                           float2* out, int batch, int64_t xbs, int64_t obs, hipStream_t s) {
+                           void* out, bool power, int batch, int64_t xbs, int64_t obs, hipStream_t s) {
   hipError_t e;
   switch (Np) {
     case 16: e = chan<16>(x, L, P, win, tabs, xt, batch, xbs, s); break;
@@ -114,15 +137,15 @@ hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* w
   }
   if (e != hipSuccess) return e;
   switch (P) {
-    case 4: return pair<4>(xt, Np, tabs, out, batch, obs, s);
-    case 8: return pair<8>(xt, Np, tabs, out, batch, obs, s);
-    case 16: return pair<16>(xt, Np, tabs, out, batch, obs, s);
-    case 32: return pair<32>(xt, Np, tabs, out, batch, obs, s);
-    case 64: return pair<64>(xt, Np, tabs, out, batch, obs, s);
-    case 128: return pair<128>(xt, Np, tabs, out, batch, obs, s);
-    case 256: return pair<256>(xt, Np, tabs, out, batch, obs, s);
-    case 512: return pair<512>(xt, Np, tabs, out, batch, obs, s);
-    case 1024: return pair<1024>(xt, Np, tabs, out, batch, obs, s);
+    case 4: return pair<4>(xt, Np, tabs, out, power, batch, obs, s);
+    case 8: return pair<8>(xt, Np, tabs, out, power, batch, obs, s);
+    case 16: return pair<16>(xt, Np, tabs, out, power, batch, obs, s);
+    case 32: return pair<32>(xt, Np, tabs, out, power, batch, obs, s);
+    case 64: return pair<64>(xt, Np, tabs, out, power, batch, obs, s);
+    case 128: return pair<128>(xt, Np, tabs, out, power, batch, obs, s);
+    case 256: return pair<256>(xt, Np, tabs, out, power, batch, obs, s);
+    case 512: return pair<512>(xt, Np, tabs, out, power, batch, obs, s);
+    case 1024: return pair<1024>(xt, Np, tabs, out, power, batch, obs, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -60,9 +60,11 @@ hipError_t launch_ssca_pass1_mfma(int prec, const float2* x, int N, int Np, cons
 hipError_t launch_ssca_pass2(const float2* T, int N, int Np, const float2* tabs, float2* out, int batch,
                              int64_t tbs, int64_t obs, const SelArg& sel, hipStream_t stream);
 
-// FAM of `batch` signals. x: [batch][P*L] at stride xbs; xt: [batch][Np][P] scratch; out: [batch][Np][Np][P].
+// FAM of `batch` signals. x: [batch][P*L] at stride xbs; xt: [batch][Np][P] scratch; out: complex
+// [batch][Np][Np][P], or with `power` float [batch][Np][Np][P/2] (|S|^2 of the bins |q_c| < P/4); obs in elements.
 hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs,
-                           float2* xt, float2* out, int batch, int64_t xbs, int64_t obs, hipStream_t stream);
+                           float2* xt, void* out, bool power, int batch, int64_t xbs, int64_t obs,
+                           hipStream_t stream);
 
 // ---- learned strip selector (learn.hip) ----
 constexpr int kHidden = 256;

@@ -154,3 +154,12 @@ def test_ssca_batch_errors(L):
     items[0].N, items[0].selector, items[0].mask = 1 << 16, ctypes.pointer(sel), _fake(O + 8)
     assert L.scd_ssca_batch(items, 1, None) == _lib.SCD_ERR_MODEL
     assert L.scd_last_error().startswith(b"item 0:")
+
+
+def test_fam_power_errors(L):
+    assert L.scd_fam_power_ex(None, 64, 16, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_NULL
+    assert L.scd_fam_power_ex(_fake(X), 64, 16, 2, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_fam_power_ex(_fake(X), 64, 128, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    o = _lib.ScdOpts()
+    o.precision = _lib.PRECISIONS["split_bf16"]
+    assert L.scd_fam_power_ex(_fake(X), 64, 16, 64, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
