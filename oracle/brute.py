@@ -53,6 +53,24 @@ def ssca_cell_eq2(x, win, k, q):
     return cmath.exp(-2j * math.pi * k * d / Np) * acc
 
 
+def ssca_cross_cell_eq2(x, y, win, k, q, conjugate=False):
+    """Cross SSCA cell [k][q] from Eq. (1)-(2) with two inputs: the demodulate of x at f_k (window win)
+    times the conjugate of y's one-sample demodulate y(r) exp(+i 2 pi q r / N) (Eq. (2)'s Y*). The
+    conjugate form multiplies by that demodulate itself, taken at the mirrored frequency: y(r) exp(-i 2 pi q r / N).
+    The constant exp(-i 2 pi k d / Np) relates Eq. (1) to Eq. (3) as in ``ssca_cell_eq2``."""
+    N = len(x)
+    Np = len(win)
+    d = Np // 2 - 1
+    acc = 0j
+    for n in range(N):
+        a = demodulate_eq1(x, n, k / Np, win)
+        if conjugate:
+            acc += a * y[n] * cmath.exp(-2j * math.pi * q * n / N)
+        else:
+            acc += a * (y[n] * cmath.exp(2j * math.pi * q * n / N)).conjugate()
+    return cmath.exp(-2j * math.pi * k * d / Np) * acc
+
+
 def fam_cell_eq15(x, win, L, P, k, l, q):
     """FAM cell [k][l][q] from Eq. (1) demodulates sampled at times pL and the P-point sum of Eq. (5).
 

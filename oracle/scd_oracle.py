@@ -91,6 +91,22 @@ def ssca(x, Np, win):
     return np.stack([ssca_strip(x, Np, win, k) for k in range(Np)])
 
 
+def ssca_cross_strip(x, y, Np, win, k, conjugate=False):
+    """Row k of the cross SCD of x and y (Eq. (2) with a second input y, Sec. II-A) by SSCA: the demodulate of
+    y has a one-sample window, so the channel-data product of Eq. (6) takes conj(y[n]) in place of conj(x[n]):
+    S_xy[k][q] = sum_n X_T[n][k] conj(y[n]) omega_N^{n q}. With conjugate=True the product takes y[n] itself
+    (the conjugate SCD, a library form: the paper treats the conjugated product only)."""
+    x = np.asarray(x, dtype=np.complex128)
+    y = np.asarray(y, dtype=np.complex128)
+    xg = ssca_demodulate_strip(x, Np, win, k) * (y if conjugate else np.conj(y))
+    return np.fft.fft(xg)
+
+
+def ssca_cross(x, y, Np, win, conjugate=False):
+    """Full cross (or conjugate) SSCA estimate, shape [Np][N], complex128; see ``ssca_cross_strip``."""
+    return np.stack([ssca_cross_strip(x, y, Np, win, k, conjugate) for k in range(Np)])
+
+
 def ssca_2dfft(x, Np, win, M1):
     """The paper's SSCA_2DFFT (Sec. III-B, Eq. (10)-(16)): same result as ``ssca`` via a decomposed DFT.
 

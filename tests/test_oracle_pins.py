@@ -37,6 +37,31 @@ def test_ssca_equals_eq2_direct_sum(N, Np, kind):
     assert np.abs(S - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("conjugate", [False, True])
+def test_ssca_cross_equals_eq2_direct_sum(conjugate):
+    """Cross and conjugate SSCA cells equal Eq. (2) with a second input y (y != x, both complex): pins which
+    operand is conjugated and the sign of y's frequency."""
+    N, Np = 32, 8
+    x, y = _sig(N, 3, "noise"), _sig(N, 4, "noise")
+    w = sg.hamming(Np)
+    S = O.ssca_cross(x, y, Np, w, conjugate)
+    ref = np.array([[B.ssca_cross_cell_eq2(list(x), list(y), list(w), k, q, conjugate) for q in range(N)]
+                    for k in range(Np)])
+    assert np.abs(S - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_ssca_cross_special_cases():
+    """y = x gives the auto SCD exactly; for a real x the conjugate form equals the auto SCD too; swapping the
+    roles of x and y changes the result (the cross form is not symmetric in its inputs)."""
+    N, Np = 256, 16
+    x, y = _sig(N, 5, "noise"), _sig(N, 6, "noise")
+    w = sg.hamming(Np)
+    assert np.array_equal(O.ssca_cross(x, x, Np, w), O.ssca(x, Np, w))
+    xr = x.real.astype(np.complex128)
+    assert np.array_equal(O.ssca_cross(xr, xr, Np, w, conjugate=True), O.ssca(xr, Np, w))
+    assert np.abs(O.ssca_cross(x, y, Np, w) - O.ssca_cross(y, x, Np, w)).max() > 1e-3 * np.abs(O.ssca(x, Np, w)).max()
+
+
 def test_ssca_window_orientation_matters():
     """A planted mistake (window reversed, which differs for an asymmetric window) is caught by the Eq. (2) pin."""
     N, Np = 32, 8
