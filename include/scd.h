@@ -109,6 +109,20 @@ int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out);
 int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts);
 
 /*
+ * scd_ssca_cross_ex - SSCA estimate of the cross SCD of x and y (Eq. (2) with y != x, Sec. II-A): the demodulate
+ * of y has the SSCA's one-sample window, so the channel-data product takes conj(y[n]) where scd_ssca takes
+ * conj(x[n]):
+ *   S_xy[k][q] = sum_{n=0}^{N-1} X_T[n][k] conj(y[n]) exp(-i 2 pi n q / N),   X_T[n][k] of x as in scd_ssca.
+ * conjugate != 0 gives the conjugate form, with y[n] in place of conj(y[n]) (a library form; the paper
+ * treats the conjugated product only); its cell [k][q] pairs x's demodulate at f_k with y's at q/N, so alpha
+ * there is the conjugate cycle frequency f_k + q_c/N. y = x gives exactly scd_ssca's result.
+ *   y    device, N complex values per signal, laid out like x (same opts->x_stride)
+ * Other arguments, options and errors as scd_ssca_ex, except that only SCD_FP32 is supported
+ * (SCD_ERR_UNSUPPORTED otherwise) and out must not overlap y (SCD_ERR_ALIAS). */
+int scd_ssca_cross_ex(const float* x, const float* y, int64_t N, int Np, const float* win, int conjugate, float* out,
+                      const scd_opts* opts);
+
+/*
  * scd_ssca_stage1_ex / scd_ssca_stage2_ex - the two stages of SSCA_2DFFT (Sec. III-B, Eq. (14)-(16)) as
  * separate calls, so a caller can time, pipeline or interleave them. scd_ssca_ex runs exactly stage 1
  * followed by stage 2 through a library-owned intermediate.

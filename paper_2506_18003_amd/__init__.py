@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -92,6 +92,30 @@ def ssca(x, Np: int, win=None, precision="fp32", out=None, workspace=None):
     o = _opts(x, precision, B, xs, Np * N, workspace)
     with torch.cuda.device(x.device):
         _lib.check(_lib.lib().scd_ssca_ex(x.data_ptr(), N, Np, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def ssca_cross(x, y, Np: int, win=None, conjugate=False, out=None, workspace=None):
+    """Cross SCD of x and y by SSCA (conj(y[n]) in the channel-data product; y[n] with conjugate=True);
+    x and y alike ([N] or [B, N]); see scd_ssca_cross_ex."""
+    torch = _torch()
+    _check_x(x)
+    _check_x(y)
+    if y.shape != x.shape or y.device != x.device or (x.dim() == 2 and y.stride(0) != x.stride(0)):
+        raise ValueError("y must have x's shape, device and row stride")
+    N = x.shape[-1]
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, N) if x.dim() == 1 else (B, Np, N)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, "fp32", B, xs, Np * N, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_cross_ex(x.data_ptr(), y.data_ptr(), N, Np, w.data_ptr(), int(bool(conjugate)),
+                                                out.data_ptr(), ctypes.byref(o)))
     return out
 
 

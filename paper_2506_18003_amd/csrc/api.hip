@@ -230,10 +230,12 @@ enum class SscaPart { kWhole, kStage1, kStage2 };
 
 // Shared validation and dispatch of the SSCA entry points. For kStage1 `in` is x and `dst` the intermediate;
 // for kStage2 `in` is the intermediate and `dst` the output (win unused); for kWhole `in` is x and `dst` out.
+// ymode: 0 the auto SCD; 1 the cross SCD of `in` and y; 2 the conjugate form (whole transform, FP32 only).
 int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* win, float* dst,
-                const scd_opts* opts, const scd::SelArg* selp = nullptr) {
+                const scd_opts* opts, const scd::SelArg* selp = nullptr, const float* y = nullptr, int ymode = 0) {
   const bool need_win = part != SscaPart::kStage2;
   if (!in || !dst || (need_win && !win)) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
+  if (ymode != 0 && !y) return fail(SCD_ERR_NULL, "y must be non-NULL");
   if (!is_pow2(N) || N < 1024 || N > (1 << 20))
     return fail(SCD_ERR_SIZE, "N = %lld must be a power of two in [2^10, 2^20]", static_cast<long long>(N));
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
@@ -245,15 +247,17 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   if (r.precision < SCD_FP32 || r.precision > SCD_FP16) return fail(SCD_ERR_SIZE, "unknown precision %d", r.precision);
   if (r.precision != SCD_FP32 && part != SscaPart::kStage2 && Np > 128)
     return fail(SCD_ERR_UNSUPPORTED, "16-bit channelizer precisions support Np <= 128 (got %d)", Np);
+  if (ymode != 0 && r.precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "the cross forms run in FP32 only");
   const size_t ib = span_bytes(r.batch, r.xs, inlen);
   const size_t ob = span_bytes(r.batch, r.os, grid);
   const size_t wb = need_win ? 4u * static_cast<size_t>(Np) : 0;
   if (overlaps(dst, ob, in, ib) || overlaps(dst, ob, win, wb)) return fail(SCD_ERR_ALIAS, "output overlaps an input");
+  if (ymode != 0 && overlaps(dst, ob, y, ib)) return fail(SCD_ERR_ALIAS, "output overlaps y");
   const size_t per = (part == SscaPart::kWhole && N > 1024) ? 8u * static_cast<size_t>(grid) : 0;
   if (part == SscaPart::kWhole && r.work) {
     if (overlaps(r.work, r.work_bytes, in, ib) || overlaps(r.work, r.work_bytes, dst, ob) ||
-        overlaps(r.work, r.work_bytes, win, wb))
-      return fail(SCD_ERR_ALIAS, "workspace overlaps x, win or out");
+        overlaps(r.work, r.work_bytes, win, wb) || (ymode != 0 && overlaps(r.work, r.work_bytes, y, ib)))
+      return fail(SCD_ERR_ALIAS, "workspace overlaps x, y, win or out");
     if (per > 0 && r.work_bytes < per)
       return fail(SCD_ERR_NOMEM, "workspace of %zu bytes is smaller than one intermediate (%zu)", r.work_bytes, per);
   }
@@ -261,6 +265,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   std::lock_guard<std::mutex> lk(g_mu);
   if ((rc = check_device_range(in, ib, part == SscaPart::kStage2 ? "intermediate" : "x"))) return rc;
   if (need_win && (rc = check_device_range(win, wb, "win"))) return rc;
+  if (ymode != 0 && (rc = check_device_range(y, ib, "y"))) return rc;
   if ((rc = check_device_range(dst, ob, part == SscaPart::kStage1 ? "intermediate" : "out"))) return rc;
   if (part == SscaPart::kWhole && r.work && (rc = check_device_range(r.work, r.work_bytes, "workspace"))) return rc;
   int dev;
@@ -275,7 +280,10 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   const scd::SelArg sel = selp ? *selp : scd::selarg_all(Np);
   // Stage 1 in the requested precision, for nb signals.
   auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
-    if (prec == SCD_FP32) return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, T, nb, r.xs, tbs, sel, r.stream);
+    if (prec == SCD_FP32) {
+      const float2* ys = ymode ? reinterpret_cast<const float2*>(y) + (xs - ic) : nullptr;
+      return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, T, nb, r.xs, tbs, sel, r.stream, ys, ymode);
+    }
     void* aux = nullptr;
     if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
     return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, sel, r.stream);
@@ -321,6 +329,11 @@ extern "C" {
 
 int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts) {
   return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts);
+}
+
+int scd_ssca_cross_ex(const float* x, const float* y, int64_t N, int Np, const float* win, int conjugate, float* out,
+                      const scd_opts* opts) {
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts, nullptr, y, conjugate ? 2 : 1);
 }
 
 int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out) {

@@ -62,11 +62,14 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 // last radix stage stores to HBM, multiplying by the rotation factor omega_N^{m2 m1'} from a per-workgroup
 // LDS table. These are plain (cached) stores: measured faster than nontemporal ones here, while Stage 2,
 // which streams T in and S out once, keeps nontemporal loads and stores.
-template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR>
+//
+// YM selects the second input of the channel-data product: 0 the auto SCD (conj(x[n]) from the fold), 1 the
+// cross SCD (conj(y[n]), Eq. (2) with y != x), 2 the conjugate form (y[n]); the cross forms load y[n].
+template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR, int YM>
 __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) void ssca_pass1_fp32(
-    const float2* __restrict__ x, int N, int M2, int m2shift, const float* __restrict__ win,
-    const float2* __restrict__ tabs, float2* __restrict__ T, int64_t xbs, int64_t tbs,
-    const ChanSel* __restrict__ sel) {
+    const float2* __restrict__ x, const float2* __restrict__ y, int N, int M2, int m2shift,
+    const float* __restrict__ win, const float2* __restrict__ tabs, float2* __restrict__ T, int64_t xbs,
+    int64_t tbs, const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
   constexpr int D = NP / 2 - 1;
   constexpr int NH = PAIR ? 2 : 1;      // channel subsets per workgroup
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       const int row = (FPR * r + fi) * kURow + jcol;
       // Tap j = D of frame m1 is the frame's own sample x[n] (n - D + j = n): the lane of residue D mod 16
       // holds it as tap D / 16 and parks it in the row's padding slot for the channel-data product.
-      if (j0 == (D & 15)) ub[(FPR * r + fi) * kURow + 16] = ring[g % PF][D >> 4];
+      if (YM == 0 && j0 == (D & 15)) ub[(FPR * r + fi) * kURow + 16] = ring[g % PF][D >> 4];
       if constexpr (PAIR) {
         float2 ea = cmul(hl[0], ring[g % PF][0]);
         float2 eb = cmul(hl[1], ring[g % PF][1]);
@@ -164,7 +167,13 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     for (int j = 0; j < 16; ++j) u[j] = ub[half * kUBuf + t * kURow + j];
     dft16(u);
     const int n = (t + 256 * f) * M2 + m2;
-    const float2 xn = ub[t * kURow + 16];
+    float2 xn;  // the sample whose conjugate the channel-data product takes
+    if constexpr (YM == 0) {
+      xn = ub[t * kURow + 16];
+    } else {
+      xn = load_c64(make_rsrc(y + blockIdx.y * xbs, N * 8), n);
+      if constexpr (YM == 2) xn = cconj(xn);
+    }
     const float2 xp = cmulc(xn, cphase);  // x[n] conj(omega_Np^{c m2})
 #pragma unroll
     for (int kp = 0; kp < 16; ++kp) {
@@ -343,25 +352,29 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
 
 template <int NP>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs,
-                 float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
+                 float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s,
+                 const float2* y, int ymode) {
   if (sel.nsub <= 0) return hipSuccess;
+  if (ymode != 0 && sel.dev) return hipErrorInvalidValue;  // the cross forms run on every strip
   // Subset pairs halve the x traffic and the fold work per strip; they are used when the paired grid still
   // gives every CU a workgroup (otherwise, e.g. for short segments, twice as many single-subset workgroups
   // finish sooner).
   auto go = [&](auto kern, bool pair) {
     dim3 grid(M2 * (pair ? sel.npair : sel.nsub), batch);
-    hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, N, M2, m2shift, win, tabs, T, xbs,
-                       tbs, sel.dev);
+    hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, y, N, M2, m2shift, win, tabs, T,
+                       xbs, tbs, sel.dev);
+  };
+  auto launch_phase = [&](auto pair_tag, auto phase_tag) {
+    constexpr bool PAIR = decltype(pair_tag)::value;
+    constexpr bool PH = decltype(phase_tag)::value;
+    if (sel.dev) go(ssca_pass1_fp32<NP, PH, true, PAIR, 0>, PAIR);
+    else if (ymode == 1) go(ssca_pass1_fp32<NP, PH, false, PAIR, 1>, PAIR);
+    else if (ymode == 2) go(ssca_pass1_fp32<NP, PH, false, PAIR, 2>, PAIR);
+    else go(ssca_pass1_fp32<NP, PH, false, PAIR, 0>, PAIR);
   };
   auto launch = [&](auto pair_tag) {
-    constexpr bool PAIR = decltype(pair_tag)::value;
-    if (M2 % NP == 0) {
-      if (sel.dev) go(ssca_pass1_fp32<NP, true, true, PAIR>, PAIR);
-      else go(ssca_pass1_fp32<NP, true, false, PAIR>, PAIR);
-    } else {
-      if (sel.dev) go(ssca_pass1_fp32<NP, false, true, PAIR>, PAIR);
-      else go(ssca_pass1_fp32<NP, false, false, PAIR>, PAIR);
-    }
+    if (M2 % NP == 0) launch_phase(pair_tag, std::true_type{});
+    else launch_phase(pair_tag, std::false_type{});
   };
   if constexpr (NP >= 32) {
     if (static_cast<int64_t>(M2) * sel.npair * batch >= kPairMinBlocks) launch(std::true_type{});
@@ -387,16 +400,17 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int ba
 }  // namespace
 
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs,
-                                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s) {
+                                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s,
+                                  const float2* y, int ymode) {
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
-    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
-    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
-    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
-    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s);
+    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
+    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
+    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
+    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
+    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
     default: return hipErrorInvalidValue;
   }
 }

@@ -163,3 +163,13 @@ def test_fam_power_errors(L):
     o = _lib.ScdOpts()
     o.precision = _lib.PRECISIONS["split_bf16"]
     assert L.scd_fam_power_ex(_fake(X), 64, 16, 64, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
+
+
+def test_ssca_cross_errors(L):
+    assert L.scd_ssca_cross_ex(_fake(X), None, 4096, 64, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_NULL
+    assert L.scd_ssca_cross_ex(_fake(X), _fake(X + 0x100000), 3000, 64, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_cross_ex(_fake(X), _fake(O), 4096, 64, _fake(W), 1, _fake(O), None) == _lib.SCD_ERR_ALIAS
+    o = _lib.ScdOpts()
+    o.precision = _lib.PRECISIONS["split_bf16"]
+    assert L.scd_ssca_cross_ex(_fake(X), _fake(X + 0x100000), 4096, 64, _fake(W), 0, _fake(O),
+                               ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
