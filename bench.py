@@ -11,9 +11,12 @@ when flops per algorithmic HBM byte exceed the ridge point (Stage 1), algorithmi
 otherwise (Stage 2); `per_kernel` gives both kernels both ways. `cpu_baseline` times the FP64 oracle on this host
 (single-threaded numpy) over all 64 strips of the same signal, which also gives the error of every GPU form
 against it. A `fam` object times the FFT accumulation method on the batch workload (16 signals of 16384
-samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes.
+samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes, with `power_form` timing the paper's
+output form (|S|^2 of the kept bins). A `cross` object times the cross SCD of the headline signal and its
+delayed copy.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline] [--no-fam]
+                       [--no-cross]
        python bench.py --write-traffic FETCH_CSV WRITE_CSV   (no GPU: summarise two rocprofv3 --pmc runs of
        `bench.py --copy-calib --forms fp32`, one with FETCH_SIZE and one with WRITE_SIZE, into the committed
        per-launch HBM traffic of the SSCA kernels)
@@ -62,7 +65,7 @@ def measured_traffic(kernel: str, digest: str):
 
 
 CALIB_BYTES = 256 << 20          # the --copy-calib kernel reads and writes this many bytes
-TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32", "ssca_pass2": "ssca_pass2_fp32"}
+TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32<64, true, false, true, 0>", "ssca_pass2": "ssca_pass2_fp32"}
 
 
 def write_traffic(fetch_csv: str, write_csv: str) -> dict:
@@ -112,6 +115,7 @@ def main():
     ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fam", action="store_true", help="skip the FAM batch measurement")
+    ap.add_argument("--no-cross", action="store_true", help="skip the cross-SCD measurement")
     ap.add_argument("--mix-signals", type=int, default=8,
                     help="held-out selector-recipe signals for the learned form's mixed-workload line (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -231,6 +235,27 @@ def main():
         results[form] = dict(ms_per_step=ms, pass1_ms=float(np.mean(p1)), pass2_ms=float(np.mean(p2)),
                              step_ms_p10=tot[len(tot) // 10], step_ms_p50=tot[len(tot) // 2],
                              step_ms_p90=tot[(9 * len(tot)) // 10], out=out.cpu().numpy())
+
+    # The cross SCD of x and its delayed copy y(n) = x(n + 5) (Eq. (2)'s two-input form with the paper's
+    # time-delay example), one scd_ssca_cross_ex call per step on the same workload.
+    cross_info = None
+    if "fp32" in forms and not args.no_cross:
+        yd = torch.zeros_like(x)
+        yd[:-5] = x[5:]
+        for _ in range(args.warmup):
+            scd.ssca_cross(x, yd, Np, win=win, out=out)
+        cev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            cev[i][0].record(stream)
+            scd.ssca_cross(x, yd, Np, win=win, out=out)
+            cev[i][1].record(stream)
+        torch.cuda.synchronize()
+        cms = float(np.mean([e[0].elapsed_time(e[1]) for e in cev]))
+        cross_info = {"workload": "cross SCD of the headline signal x and y(n) = x(n + 5), N=2^20, Np=64",
+                      "ms_per_step": round(cms, 5), "pts_per_s": round(Np * N / (cms * 1e-3), 1),
+                      "speedup_vs_fp32_auto": round(results["fp32"]["ms_per_step"] / cms, 3)}
+        del yd
 
     # Algorithmic HBM bytes and flops per launch (one signal). Pass 1 reads x and writes the intermediate;
     # pass 2 reads and writes Np*N complex values. Flops follow the paper's convention (5 n log2 n per n-point
@@ -381,6 +406,8 @@ def main():
             line["forms"]["learned"]["mix"] = dict(
                 workload=f"{li['mix']['signals']} held-out signals of the selector recipe at N=2^20, Np={Np}",
                 **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in li["mix"].items()})
+    if cross_info is not None:
+        line["cross"] = cross_info
     print(json.dumps(line), flush=True)
 
 
