@@ -89,6 +89,21 @@ def fam_cell_eq15(x, win, L, P, k, l, q):
     return cmath.exp(-2j * math.pi * (k - l) * d / Np) * acc
 
 
+def fam_cross_cell_eq15(x, y, win, L, P, k, l, q, conjugate=False):
+    """Cross FAM cell [k][l][q]: Eq. (1) demodulates of x at f_k and of y at f_l, sampled at pL, their
+    Eq. (2) product (y's conjugated, or not in the conjugate form) and the P-point sum of Eq. (5). The Eq. (3)
+    form differs by exp(-i 2 pi (k - l) d / Np), or exp(-i 2 pi (k + l) d / Np) in the conjugate form."""
+    xs, ys = list(x[: P * L]), list(y[: P * L])
+    Np = len(win)
+    d = Np // 2 - 1
+    acc = 0j
+    for p in range(P):
+        a = demodulate_eq1(xs, p * L, k / Np, win)
+        b = demodulate_eq1(ys, p * L, l / Np, win)
+        acc += a * (b if conjugate else b.conjugate()) * cmath.exp(-2j * math.pi * p * q / P)
+    return cmath.exp(-2j * math.pi * (k + l if conjugate else k - l) * d / Np) * acc
+
+
 def channelize_direct(x, Np, L, P, win):
     """Eq. (3) written as a double loop (no FFT): X_T[p][k]."""
     d = Np // 2 - 1

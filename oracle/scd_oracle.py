@@ -165,6 +165,19 @@ def fam(x, Np, L, P, win):
     return np.ascontiguousarray(s.transpose(1, 2, 0))
 
 
+def fam_cross(x, y, Np, L, P, win, conjugate=False):
+    """Cross FAM of x and y (Eq. (2) and (5) with a second input): S_xy[k][l][q] =
+    sum_p X_T[p][k] conj(Y_T[p][l]) omega_P^{p q}, Y_T the Eq. (3) channelizer output of y. With
+    conjugate=True the product takes Y_T[p][l] itself (the conjugate SCD, a library form)."""
+    x = np.asarray(x, dtype=np.complex128)[: P * L]
+    y = np.asarray(y, dtype=np.complex128)[: P * L]
+    xt = channelize(x, Np, L, P, win)
+    yt = channelize(y, Np, L, P, win)
+    z = xt[:, :, None] * (yt if conjugate else np.conj(yt))[:, None, :]
+    s = np.fft.fft(z, axis=0)
+    return np.ascontiguousarray(s.transpose(1, 2, 0))
+
+
 def fam_coords(Np, L, P):
     """(f, alpha) of each FAM cell [k][l][q]: f = (f_k + f_l)/2, alpha = f_k - f_l + q_c/(P L)."""
     k = np.arange(Np)

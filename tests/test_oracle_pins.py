@@ -62,6 +62,24 @@ def test_ssca_cross_special_cases():
     assert np.abs(O.ssca_cross(x, y, Np, w) - O.ssca_cross(y, x, Np, w)).max() > 1e-3 * np.abs(O.ssca(x, Np, w)).max()
 
 
+@pytest.mark.parametrize("conjugate", [False, True])
+def test_fam_cross_equals_eq5_direct_sum(conjugate):
+    """Cross and conjugate FAM cells equal the Eq. (5) sums of Eq. (1) demodulates of x and y (y != x)."""
+    Np, L, P = 8, 2, 8
+    x, y = _sig(P * L, 7, "noise"), _sig(P * L, 8, "noise")
+    w = sg.hamming(Np)
+    S = O.fam_cross(x, y, Np, L, P, w, conjugate)
+    ref = np.array([[[B.fam_cross_cell_eq15(x, y, list(w), L, P, k, l, q, conjugate) for q in range(P)]
+                     for l in range(Np)] for k in range(Np)])
+    assert np.abs(S - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fam_cross_with_itself_is_the_auto_fam():
+    x = _sig(256, 9, "bpsk")
+    w = sg.hamming(16)
+    assert np.array_equal(O.fam_cross(x, x, 16, 4, 64, w), O.fam(x, 16, 4, 64, w))
+
+
 def test_ssca_window_orientation_matters():
     """A planted mistake (window reversed, which differs for an asymmetric window) is caught by the Eq. (2) pin."""
     N, Np = 32, 8
