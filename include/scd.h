@@ -170,6 +170,15 @@ int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* ou
  * bytes, which dominate FAM's HBM traffic. */
 int scd_fam_power_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
 
+/* scd_fam_cross_ex - FAM estimate of the cross SCD of x and y (Eq. (2) and (5) with a second input):
+ *   S_xy[k][l][q] = sum_p X_T[p][k] conj(Y_T[p][l]) exp(-i 2 pi p q / P),   Y_T the Eq. (3) channelizer of y;
+ * conjugate != 0 takes Y_T[p][l] itself (the conjugate SCD, a library form). y = x gives scd_fam's result.
+ *   y    device, P*L complex values per signal, laid out like x (same opts->x_stride)
+ * A caller workspace must hold X_T and Y_T: twice what scd_fam_workspace_size reports. Other arguments,
+ * options and errors as scd_fam_ex; out must not overlap y (SCD_ERR_ALIAS). */
+int scd_fam_cross_ex(const float* x, const float* y, int Np, int L, int P, const float* win, int conjugate, float* out,
+                     const scd_opts* opts);
+
 /* ---------------------------------------------------------------------------------------------------------
  * Learned strip selection. The paper has no learned component (its glossary only names the averaged cyclic
  * periodogram and the PSD, and its conclusion points at a machine-learning back-end); the definitions below

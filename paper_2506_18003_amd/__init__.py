@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_cross", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -209,6 +209,36 @@ def fam(x, Np: int, L: int | None = None, P: int | None = None, win=None, out=No
     o = _opts(x, "fp32", B, xs, Np * Np * P, workspace)
     with torch.cuda.device(x.device):
         _lib.check(_lib.lib().scd_fam_ex(x.data_ptr(), Np, L, P, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
+def fam_cross(x, y, Np: int, L: int | None = None, P: int | None = None, win=None, conjugate=False, out=None,
+              workspace=None):
+    """Cross FAM of x and y (conj(Y_T) in the product; Y_T itself with conjugate=True), x and y alike;
+    see scd_fam_cross_ex."""
+    torch = _torch()
+    _check_x(x)
+    _check_x(y)
+    if y.shape != x.shape or y.device != x.device or (x.dim() == 2 and y.stride(0) != x.stride(0)):
+        raise ValueError("y must have x's shape, device and row stride")
+    if L is None:
+        L = Np // 4
+    if P is None:
+        P = x.shape[-1] // L
+    if x.shape[-1] < P * L:
+        raise ValueError(f"x has {x.shape[-1]} samples, FAM needs P*L = {P * L}")
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, Np, P) if x.dim() == 1 else (B, Np, Np, P)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, "fp32", B, xs, Np * Np * P, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_fam_cross_ex(x.data_ptr(), y.data_ptr(), Np, L, P, w.data_ptr(),
+                                               int(bool(conjugate)), out.data_ptr(), ctypes.byref(o)))
     return out
 
 

@@ -80,6 +80,8 @@ _SIGS = {
     "scd_ssca_stage2_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdOpts)]),
     "scd_fam": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]),
     "scd_fam_ex": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
+    "scd_fam_cross_ex": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int, _P,
+                                        ctypes.POINTER(ScdOpts)]),
     "scd_fam_power_ex": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P,
                                         ctypes.POINTER(ScdOpts)]),
     "scd_ssca_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int,

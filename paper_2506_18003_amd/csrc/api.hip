@@ -354,7 +354,7 @@ namespace {
 
 // FAM of Eq. (3)-(5); `power` selects the |S|^2 form over |q_c| < P/4 (float output, P/2 bins per pair).
 int fam_common(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts,
-               bool power) {
+               bool power, const float* y = nullptr, bool conj = false) {
   if (!x || !win || !out) return fail(SCD_ERR_NULL, "x, win and out must be non-NULL");
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
   if (!is_pow2(L) || L > Np) return fail(SCD_ERR_SIZE, "L = %d must be a power of two in [1, Np]", L);
@@ -370,16 +370,19 @@ int fam_common(const float* x, int Np, int L, int P, const float* win, float* ou
   const size_t ob = span_bytes(r.batch, r.os, olen) / (power ? 2 : 1);  // float elements in the power form
   const size_t wb = 4u * static_cast<size_t>(Np);
   if (overlaps(out, ob, x, xb) || overlaps(out, ob, win, wb)) return fail(SCD_ERR_ALIAS, "out overlaps x or win");
-  const size_t per = 8u * static_cast<size_t>(Np) * static_cast<size_t>(P);
+  if (y && overlaps(out, ob, y, xb)) return fail(SCD_ERR_ALIAS, "out overlaps y");
+  // X_T per signal, and Y_T beside it in the cross forms.
+  const size_t per = 8u * static_cast<size_t>(Np) * static_cast<size_t>(P) * (y ? 2 : 1);
   if (r.work && (overlaps(r.work, r.work_bytes, x, xb) || overlaps(r.work, r.work_bytes, out, ob) ||
-                 overlaps(r.work, r.work_bytes, win, wb)))
-    return fail(SCD_ERR_ALIAS, "workspace overlaps x, win or out");
+                 overlaps(r.work, r.work_bytes, win, wb) || (y && overlaps(r.work, r.work_bytes, y, xb))))
+    return fail(SCD_ERR_ALIAS, "workspace overlaps x, y, win or out");
   if (r.work && r.work_bytes < per)
     return fail(SCD_ERR_NOMEM, "workspace of %zu bytes is smaller than one X_T (%zu)", r.work_bytes, per);
 
   std::lock_guard<std::mutex> lk(g_mu);
   if ((rc = check_device_range(x, xb, "x"))) return rc;
   if ((rc = check_device_range(win, wb, "win"))) return rc;
+  if (y && (rc = check_device_range(y, xb, "y"))) return rc;
   if ((rc = check_device_range(out, ob, "out"))) return rc;
   if (r.work && (rc = check_device_range(r.work, r.work_bytes, "workspace"))) return rc;
   int dev;
@@ -395,8 +398,9 @@ int fam_common(const float* x, int Np, int L, int P, const float* win, float* ou
   for (int b0 = 0; b0 < r.batch; b0 += chunk) {
     const int nb = std::min(chunk, r.batch - b0);
     void* oc = power ? static_cast<void*>(out + b0 * r.os) : static_cast<void*>(reinterpret_cast<float2*>(out) + b0 * r.os);
+    const float2* yc = y ? reinterpret_cast<const float2*>(y) + b0 * r.xs : nullptr;
     hipError_t e = scd::launch_fam_fp32(xc + b0 * r.xs, Np, L, P, win, tabs, static_cast<float2*>(work), oc,
-                                        power, nb, r.xs, r.os, r.stream);
+                                        power, nb, r.xs, r.os, r.stream, yc, conj);
     if (e != hipSuccess) return hip_fail(e, "FAM launch");
   }
   return SCD_OK;
@@ -412,6 +416,12 @@ int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* ou
 
 int scd_fam_power_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts) {
   return fam_common(x, Np, L, P, win, out, opts, true);
+}
+
+int scd_fam_cross_ex(const float* x, const float* y, int Np, int L, int P, const float* win, int conjugate, float* out,
+                     const scd_opts* opts) {
+  if (!y) return fail(SCD_ERR_NULL, "y must be non-NULL");
+  return fam_common(x, Np, L, P, win, out, opts, false, y, conjugate != 0);
 }
 
 int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out) {

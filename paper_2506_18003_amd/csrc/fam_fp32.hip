@@ -65,8 +65,11 @@ __device__ __forceinline__ float power_rn(float2 v) {
   return v.x * v.x + v.y * v.y;
 }
 
-template <int P, bool POWER>
-__global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __restrict__ xt, int Np,
+// Rows l come from yt: X_T itself for the auto SCD, y's channelizer output for the cross SCD. CONJ multiplies
+// by Y_T[p][l] itself (the conjugate form) instead of its conjugate.
+template <int P, bool POWER, bool CONJ>
+__global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __restrict__ xt,
+                                                             const float2* __restrict__ yt, int Np,
                                                              const float2* __restrict__ tabs,
                                                              void* __restrict__ out, int64_t xtbs,
                                                              int64_t obs) {
@@ -78,11 +81,12 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
   const int l0 = blockIdx.x * kLT;
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
+  yt += blockIdx.z * xtbs;
   for (int i = tid; i < TWN; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i * (1024 / TWN)];
   for (int i = tid; i < P; i += kPairThreads) rk[i] = xt[static_cast<int64_t>(k) * P + i];
   __syncthreads();
-  const float2* rl = xt + static_cast<int64_t>(l0) * P;
-  auto ld = [&](int b, int m) { return cmulc(rk[m], rl[b * P + m]); };
+  const float2* rl = yt + static_cast<int64_t>(l0) * P;
+  auto ld = [&](int b, int m) { return CONJ ? cmul(rk[m], rl[b * P + m]) : cmulc(rk[m], rl[b * P + m]); };
   // The output is written once and never read back here: stream it past the caches.
   if constexpr (POWER) {
     constexpr int H = P / 4;
@@ -110,42 +114,55 @@ hipError_t chan(const float2* x, int L, int P, const float* win, const float2* t
 }
 
 template <int P>
-hipError_t pair(const float2* xt, int Np, const float2* tabs, void* out, bool power, int batch, int64_t obs,
-                hipStream_t s) {
+hipError_t pair(const float2* xt, const float2* yt, bool conj, int Np, const float2* tabs, void* out, bool power,
+                int batch, int64_t obs, hipStream_t s) {
   dim3 grid(Np / kLT, Np, batch);
+  const int64_t xtbs = static_cast<int64_t>(Np) * P;
   if (power)
-    hipLaunchKernelGGL((fam_pair_fp32<P, true>), grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
-                       static_cast<int64_t>(Np) * P, obs);
+    hipLaunchKernelGGL((fam_pair_fp32<P, true, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
+  else if (conj)
+    hipLaunchKernelGGL((fam_pair_fp32<P, false, true>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
   else
-    hipLaunchKernelGGL((fam_pair_fp32<P, false>), grid, dim3(kPairThreads), 0, s, xt, Np, tabs, out,
-                       static_cast<int64_t>(Np) * P, obs);
+    hipLaunchKernelGGL((fam_pair_fp32<P, false, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs, float2* xt,
-                           void* out, bool power, int batch, int64_t xbs, int64_t obs, hipStream_t s) {
-  hipError_t e;
-  switch (Np) {
-    case 16: e = chan<16>(x, L, P, win, tabs, xt, batch, xbs, s); break;
-    case 32: e = chan<32>(x, L, P, win, tabs, xt, batch, xbs, s); break;
-    case 64: e = chan<64>(x, L, P, win, tabs, xt, batch, xbs, s); break;
-    case 128: e = chan<128>(x, L, P, win, tabs, xt, batch, xbs, s); break;
-    case 256: e = chan<256>(x, L, P, win, tabs, xt, batch, xbs, s); break;
-    default: return hipErrorInvalidValue;
-  }
+                           void* out, bool power, int batch, int64_t xbs, int64_t obs, hipStream_t s,
+                           const float2* y, bool conj) {
+  auto channelize = [&](const float2* in, float2* dst) -> hipError_t {
+    switch (Np) {
+      case 16: return chan<16>(in, L, P, win, tabs, dst, batch, xbs, s);
+      case 32: return chan<32>(in, L, P, win, tabs, dst, batch, xbs, s);
+      case 64: return chan<64>(in, L, P, win, tabs, dst, batch, xbs, s);
+      case 128: return chan<128>(in, L, P, win, tabs, dst, batch, xbs, s);
+      case 256: return chan<256>(in, L, P, win, tabs, dst, batch, xbs, s);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  hipError_t e = channelize(x, xt);
   if (e != hipSuccess) return e;
+  // The cross forms channelize y into the second half of the scratch.
+  float2* yt = xt;
+  if (y) {
+    yt = xt + static_cast<int64_t>(batch) * Np * P;
+    if ((e = channelize(y, yt)) != hipSuccess) return e;
+  }
   switch (P) {
-    case 4: return pair<4>(xt, Np, tabs, out, power, batch, obs, s);
-    case 8: return pair<8>(xt, Np, tabs, out, power, batch, obs, s);
-    case 16: return pair<16>(xt, Np, tabs, out, power, batch, obs, s);
-    case 32: return pair<32>(xt, Np, tabs, out, power, batch, obs, s);
-    case 64: return pair<64>(xt, Np, tabs, out, power, batch, obs, s);
-    case 128: return pair<128>(xt, Np, tabs, out, power, batch, obs, s);
-    case 256: return pair<256>(xt, Np, tabs, out, power, batch, obs, s);
-    case 512: return pair<512>(xt, Np, tabs, out, power, batch, obs, s);
-    case 1024: return pair<1024>(xt, Np, tabs, out, power, batch, obs, s);
+    case 4: return pair<4>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 8: return pair<8>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 16: return pair<16>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 32: return pair<32>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 64: return pair<64>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 128: return pair<128>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 256: return pair<256>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 512: return pair<512>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    case 1024: return pair<1024>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
     default: return hipErrorInvalidValue;
   }
 }

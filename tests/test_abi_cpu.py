@@ -173,3 +173,9 @@ def test_ssca_cross_errors(L):
     o.precision = _lib.PRECISIONS["split_bf16"]
     assert L.scd_ssca_cross_ex(_fake(X), _fake(X + 0x100000), 4096, 64, _fake(W), 0, _fake(O),
                                ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
+
+
+def test_fam_cross_errors(L):
+    assert L.scd_fam_cross_ex(_fake(X), None, 64, 16, 64, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_NULL
+    assert L.scd_fam_cross_ex(_fake(X), _fake(X + 0x100000), 64, 16, 2, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_fam_cross_ex(_fake(X), _fake(O), 64, 16, 64, _fake(W), 1, _fake(O), None) == _lib.SCD_ERR_ALIAS

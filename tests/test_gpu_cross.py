@@ -55,3 +55,32 @@ def test_cross_batch_paired_stage1(dev):
 def test_cross_with_itself_is_the_auto_scd(dev):
     x = _g(sg.qpsk(1 << 15, 0.1, 8, 5.0, sg.rng_for(102, 0)), dev)
     assert torch.equal(scd.ssca_cross(x, x, 64), scd.ssca(x, 64))
+
+
+@pytest.mark.parametrize("conjugate", [False, True])
+@pytest.mark.parametrize("Np,L,P", [(16, 4, 64), (64, 16, 128), (256, 64, 32), (32, 1, 1024), (16, 16, 4)])
+def test_fam_cross_matches_oracle(dev, Np, L, P, conjugate):
+    x = sg.bpsk(P * L, 0.06, 6, 2.0, sg.rng_for(103, Np + P)).astype(np.complex64)
+    y = sg.msk(P * L, 0.11, 8, 4.0, sg.rng_for(104, Np + P)).astype(np.complex64)
+    w = sg.hamming(Np).astype(np.float32)
+    S = scd.fam_cross(_g(x, dev), _g(y, dev), Np, L, P, win=torch.from_numpy(w).to(dev), conjugate=conjugate)
+    ref = O.fam_cross(x.astype(np.complex128), y.astype(np.complex128), Np, L, P, w.astype(np.float64), conjugate)
+    assert _rel(S.cpu().numpy(), ref) <= TOL_FP32
+
+
+def test_fam_cross_batch_and_small_workspace(dev):
+    """A batch of three through a caller workspace that holds one signal's X_T and Y_T (so three chunks)."""
+    Np, L, P = 64, 16, 64
+    xs = np.stack([sg.qpsk(P * L, 0.1, 8, 0.0, sg.rng_for(105, b)) for b in range(3)]).astype(np.complex64)
+    ys = np.stack([sg.noise(P * L, sg.rng_for(106, b)) for b in range(3)]).astype(np.complex64)
+    ws = torch.empty(2 * scd.fam_workspace_size(Np, L, P) // 8, dtype=torch.complex64, device=dev)
+    S = scd.fam_cross(_g(xs, dev), _g(ys, dev), Np, L, P, workspace=ws).cpu().numpy()
+    w = sg.hamming(Np).astype(np.float32).astype(np.float64)
+    for b in range(3):
+        ref = O.fam_cross(xs[b].astype(np.complex128), ys[b].astype(np.complex128), Np, L, P, w)
+        assert _rel(S[b], ref) <= TOL_FP32, b
+
+
+def test_fam_cross_with_itself_is_the_auto_fam(dev):
+    x = _g(sg.bpsk(4096, 0.08, 5, 1.0, sg.rng_for(107, 0)), dev)
+    assert torch.equal(scd.fam_cross(x, x, 64, 16, 256), scd.fam(x, 64, 16, 256))
