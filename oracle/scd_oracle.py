@@ -91,6 +91,21 @@ def ssca(x, Np, win):
     return np.stack([ssca_strip(x, Np, win, k) for k in range(Np)])
 
 
+def ssca_block(x, offset, N, Np, win):
+    """SSCA of the block n in [offset, offset + N) of a longer signal x (a stream of blocks): the channelizer
+    of Eq. (3) runs on the whole signal, so frames at the block edges see the true neighbouring samples (zero
+    only outside x), and the sum of Eq. (7) runs over the block:
+    S[k][q] = sum_{n<N} X_T[offset + n][k] conj(x[offset + n]) omega_N^{n q}. Blocks start at multiples of Np,
+    where Eq. (3)'s down-conversion factor omega_Np^{(k n) mod Np} is the same counted from the block's start."""
+    x = np.asarray(x, dtype=np.complex128)
+    out = np.empty((Np, N), np.complex128)
+    xb = x[offset:offset + N]
+    for k in range(Np):
+        xt = ssca_demodulate_strip(x, Np, win, k)[offset:offset + N]
+        out[k] = np.fft.fft(xt * np.conj(xb))
+    return out
+
+
 def ssca_cross_strip(x, y, Np, win, k, conjugate=False):
     """Row k of the cross SCD of x and y (Eq. (2) with a second input y, Sec. II-A) by SSCA: the demodulate of
     y has a one-sample window, so the channel-data product of Eq. (6) takes conj(y[n]) in place of conj(x[n]):

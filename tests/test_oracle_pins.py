@@ -80,6 +80,27 @@ def test_fam_cross_with_itself_is_the_auto_fam():
     assert np.array_equal(O.fam_cross(x, x, 16, 4, 64, w), O.fam(x, 16, 4, 64, w))
 
 
+def test_ssca_block_pins():
+    """The block form over the whole signal is the SSCA; each block cell equals the direct Eq. (1)-(2) sum over
+    the block's times with demodulates of the whole signal (edges see the neighbouring samples). The offset is
+    a multiple of Np, so the down-conversion of Eq. (3) is the same from the block's start as from the signal's."""
+    x = _sig(64, 10, "noise")
+    w = sg.hamming(8)
+    assert np.array_equal(O.ssca_block(x, 0, 64, 8, w), O.ssca(x, 8, w))
+    off, N, Np = 16, 16, 8
+    S = O.ssca_block(x, off, N, Np, w)
+    d = Np // 2 - 1
+    xs, ws = list(x), list(w)
+    for k in range(Np):
+        for q in range(N):
+            acc = 0j
+            for n in range(N):
+                a = B.demodulate_eq1(xs, off + n, k / Np, ws)
+                acc += a * (x[off + n] * np.exp(2j * np.pi * q * n / N)).conjugate()
+            ref = np.exp(-2j * np.pi * k * d / Np) * acc
+            assert abs(S[k][q] - ref) <= 1e-12 * np.abs(S).max(), (k, q)
+
+
 def test_ssca_window_orientation_matters():
     """A planted mistake (window reversed, which differs for an asymmetric window) is caught by the Eq. (2) pin."""
     N, Np = 32, 8
