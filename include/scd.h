@@ -109,6 +109,19 @@ int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out);
 int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts);
 
 /*
+ * scd_ssca_block_ex - SSCA estimate of the block n in [offset, offset + N) of a longer signal (a stream of
+ * blocks): the channelizer of Eq. (3) sees the whole signal, so frames at the block's edges use the true
+ * neighbouring samples, with zeros only outside [0, len); the sum of Eq. (7) runs over the block:
+ *   S[k][q] = sum_{n<N} X_T[offset + n][k] conj(x[offset + n]) exp(-i 2 pi n q / N).
+ *   x       device, len complex values per signal (opts->x_stride between signals, default len)
+ *   len     samples of each signal, at most 2^27
+ *   offset  start of the block, a multiple of Np (where Eq. (3)'s down-conversion restarts), offset + N <= len
+ * offset = 0 with len = N is scd_ssca_ex. Other arguments, options and errors as scd_ssca_ex, except that only
+ * SCD_FP32 is supported (SCD_ERR_UNSUPPORTED otherwise) and a bad len or offset is SCD_ERR_SIZE. */
+int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, int Np, const float* win, float* out,
+                      const scd_opts* opts);
+
+/*
  * scd_ssca_cross_ex - SSCA estimate of the cross SCD of x and y (Eq. (2) with y != x, Sec. II-A): the demodulate
  * of y has the SSCA's one-sample window, so the channel-data product takes conj(y[n]) where scd_ssca takes
  * conj(x[n]):

@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_cross", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_block", "ssca_stream", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_cross", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -93,6 +93,32 @@ def ssca(x, Np: int, win=None, precision="fp32", out=None, workspace=None):
     with torch.cuda.device(x.device):
         _lib.check(_lib.lib().scd_ssca_ex(x.data_ptr(), N, Np, w.data_ptr(), out.data_ptr(), ctypes.byref(o)))
     return out
+
+
+def ssca_block(x, offset: int, N: int, Np: int, win=None, out=None, workspace=None):
+    """SSCA of the block [offset, offset + N) of the signal x ([len] complex64), with frames at the block's
+    edges reading the neighbouring samples; see scd_ssca_block_ex."""
+    torch = _torch()
+    _check_x(x)
+    if x.dim() != 1:
+        raise ValueError("x must be one signal [len]")
+    w = _window(win, Np, x.device)
+    if out is None:
+        out = torch.empty(Np, N, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != (Np, N) or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {(Np, N)}")
+    o = _opts(x, "fp32", 1, 0, Np * N, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_block_ex(x.data_ptr(), x.shape[0], offset, N, Np, w.data_ptr(), out.data_ptr(),
+                                                ctypes.byref(o)))
+    return out
+
+
+def ssca_stream(x, N: int, Np: int, win=None):
+    """Consecutive blocks of N samples of a resident signal x, each estimated with its true neighbours
+    (ssca_block at offsets 0, N, 2N, ...); yields (offset, S) in order, enqueued on the current stream."""
+    for off in range(0, x.shape[-1] - N + 1, N):
+        yield off, ssca_block(x, off, N, Np, win=win)
 
 
 def ssca_cross(x, y, Np: int, win=None, conjugate=False, out=None, workspace=None):

@@ -74,6 +74,8 @@ _P = ctypes.c_void_p
 _SIGS = {
     "scd_ssca": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P]),
     "scd_ssca_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
+    "scd_ssca_block_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, _P, _P,
+                                         ctypes.POINTER(ScdOpts)]),
     "scd_ssca_cross_ex": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.c_int, _P,
                                          ctypes.POINTER(ScdOpts)]),
     "scd_ssca_stage1_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),

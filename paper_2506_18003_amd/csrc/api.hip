@@ -231,8 +231,10 @@ enum class SscaPart { kWhole, kStage1, kStage2 };
 // Shared validation and dispatch of the SSCA entry points. For kStage1 `in` is x and `dst` the intermediate;
 // for kStage2 `in` is the intermediate and `dst` the output (win unused); for kWhole `in` is x and `dst` out.
 // ymode: 0 the auto SCD; 1 the cross SCD of `in` and y; 2 the conjugate form (whole transform, FP32 only).
+// xlen/xoff (whole transform, FP32): the block [xoff, xoff + N) of a signal of xlen samples; 0 = the signal.
 int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* win, float* dst,
-                const scd_opts* opts, const scd::SelArg* selp = nullptr, const float* y = nullptr, int ymode = 0) {
+                const scd_opts* opts, const scd::SelArg* selp = nullptr, const float* y = nullptr, int ymode = 0,
+                int64_t xlen = 0, int64_t xoff = 0) {
   const bool need_win = part != SscaPart::kStage2;
   if (!in || !dst || (need_win && !win)) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
   if (ymode != 0 && !y) return fail(SCD_ERR_NULL, "y must be non-NULL");
@@ -240,7 +242,14 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     return fail(SCD_ERR_SIZE, "N = %lld must be a power of two in [2^10, 2^20]", static_cast<long long>(N));
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
   const int64_t grid = static_cast<int64_t>(Np) * N;
-  const int64_t inlen = (part == SscaPart::kStage2) ? grid : N;
+  if (xlen == 0) xlen = N;
+  if (xlen != N || xoff != 0) {
+    if (xlen > (int64_t{1} << 27)) return fail(SCD_ERR_SIZE, "a signal of blocks holds at most 2^27 samples");
+    if (xoff < 0 || xoff % Np != 0 || xoff + N > xlen)
+      return fail(SCD_ERR_SIZE, "the block [%lld, %lld) must lie in [0, %lld) and start at a multiple of Np",
+                  static_cast<long long>(xoff), static_cast<long long>(xoff + N), static_cast<long long>(xlen));
+  }
+  const int64_t inlen = (part == SscaPart::kStage2) ? grid : xlen;
   Resolved r;
   int rc = resolve(opts, inlen, grid, &r);
   if (rc) return rc;
@@ -248,6 +257,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   if (r.precision != SCD_FP32 && part != SscaPart::kStage2 && Np > 128)
     return fail(SCD_ERR_UNSUPPORTED, "16-bit channelizer precisions support Np <= 128 (got %d)", Np);
   if (ymode != 0 && r.precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "the cross forms run in FP32 only");
+  if (xlen != N && r.precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "the block form runs in FP32 only");
   const size_t ib = span_bytes(r.batch, r.xs, inlen);
   const size_t ob = span_bytes(r.batch, r.os, grid);
   const size_t wb = need_win ? 4u * static_cast<size_t>(Np) : 0;
@@ -282,7 +292,8 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
     if (prec == SCD_FP32) {
       const float2* ys = ymode ? reinterpret_cast<const float2*>(y) + (xs - ic) : nullptr;
-      return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, T, nb, r.xs, tbs, sel, r.stream, ys, ymode);
+      return scd::launch_ssca_pass1_fp32(xs, n, Np, win, tabs, T, nb, r.xs, tbs, sel, r.stream, ys, ymode,
+                                         static_cast<int>(xlen), static_cast<int>(xoff));
     }
     void* aux = nullptr;
     if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
@@ -334,6 +345,12 @@ int scd_ssca_ex(const float* x, int64_t N, int Np, const float* win, float* out,
 int scd_ssca_cross_ex(const float* x, const float* y, int64_t N, int Np, const float* win, int conjugate, float* out,
                       const scd_opts* opts) {
   return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts, nullptr, y, conjugate ? 2 : 1);
+}
+
+int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, int Np, const float* win, float* out,
+                      const scd_opts* opts) {
+  if (len <= 0) return fail(SCD_ERR_SIZE, "len must be positive");
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts, nullptr, nullptr, 0, len, offset);
 }
 
 int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out) {

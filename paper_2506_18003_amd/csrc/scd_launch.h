@@ -45,10 +45,11 @@ hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 // win: device float[Np]; T: [batch] blocked intermediates [Np][M1/16][M2][16] at stride tbs (float2 elements).
 // With N == 1024 the intermediate layout equals the output layout [Np][N]. ymode 1 (cross) or 2 (conjugate)
 // takes the channel-data product with conj(y[n]) or y[n] instead of conj(x[n]); y is laid out like x, and a
-// cross form runs without a selection (sel.dev == nullptr).
+// cross form runs without a selection (sel.dev == nullptr). xlen/xoff estimate the block [xoff, xoff + N) of a
+// signal of xlen samples at x (xoff a multiple of Np; 0 and 0 = the whole signal, xlen = N).
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs, float2* T,
                                   int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t stream,
-                                  const float2* y = nullptr, int ymode = 0);
+                                  const float2* y = nullptr, int ymode = 0, int xlen = 0, int xoff = 0);
 
 // SSCA Stage 1 with the channelizer on MFMA in 16-bit (split or plain) precision, Np <= 128. scratch: device
 // memory of ssca_mfma_scratch_bytes(N, Np, batch) bytes for the 16-bit copies of x and the DFT weights,

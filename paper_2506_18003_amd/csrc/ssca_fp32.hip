@@ -67,7 +67,7 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 // cross SCD (conj(y[n]), Eq. (2) with y != x), 2 the conjugate form (y[n]); the cross forms load y[n].
 template <int NP, bool PHASE_BY_M2, bool SEL, bool PAIR, int YM>
 __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) void ssca_pass1_fp32(
-    const float2* __restrict__ x, const float2* __restrict__ y, int N, int M2, int m2shift,
+    const float2* __restrict__ x, const float2* __restrict__ y, int N, int xlen, int xoff, int M2, int m2shift,
     const float* __restrict__ win, const float2* __restrict__ tabs, float2* __restrict__ T, int64_t xbs,
     int64_t tbs, const ChanSel* __restrict__ sel) {
   constexpr int S = NP / 16;
@@ -99,7 +99,9 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
   const float2* rlo = tabs + kTabRotLo;
-  const auto xr = make_rsrc(x, N * 8);
+  // x holds xlen samples and the block starts at xoff (0 and N for a whole signal): frames at the block's
+  // edges read the neighbouring samples, and only samples outside x read as zero.
+  const auto xr = make_rsrc(x, xlen * 8);
   const int hishift = 10 - m2shift;
 
   const float2* tw_g = tabs + kTabTw1024;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   const int jcol = PHASE_BY_M2 ? ((j0 + m2) & 15) : j0;
   const float2 cphase = PHASE_BY_M2 ? tabs[kTabRoots + ((c * m2) & (NP - 1))] : make_float2(1.f, 0.f);
   // Round g folds frames m1 = FPR g + fi; its NT samples sit at x[base + 16 j1].
-  const int base0 = fi * M2 + m2 - D + j0;
+  const int base0 = xoff + fi * M2 + m2 - D + j0;
   float2 ring[PF][NT];
   auto issue = [&](int g) {
 #pragma unroll
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
 template <int NP>
 hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, const float2* tabs,
                  float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s,
-                 const float2* y, int ymode) {
+                 const float2* y, int ymode, int xlen, int xoff) {
   if (sel.nsub <= 0) return hipSuccess;
   if (ymode != 0 && sel.dev) return hipErrorInvalidValue;  // the cross forms run on every strip
   // Subset pairs halve the x traffic and the fold work per strip; they are used when the paired grid still
@@ -361,8 +363,8 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
   // finish sooner).
   auto go = [&](auto kern, bool pair) {
     dim3 grid(M2 * (pair ? sel.npair : sel.nsub), batch);
-    hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, y, N, M2, m2shift, win, tabs, T,
-                       xbs, tbs, sel.dev);
+    hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, y, N, xlen, xoff, M2, m2shift, win,
+                       tabs, T, xbs, tbs, sel.dev);
   };
   auto launch_phase = [&](auto pair_tag, auto phase_tag) {
     constexpr bool PAIR = decltype(pair_tag)::value;
@@ -401,16 +403,17 @@ hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int ba
 
 hipError_t launch_ssca_pass1_fp32(const float2* x, int N, int Np, const float* win, const float2* tabs,
                                   float2* T, int batch, int64_t xbs, int64_t tbs, const SelArg& sel, hipStream_t s,
-                                  const float2* y, int ymode) {
+                                  const float2* y, int ymode, int xlen, int xoff) {
+  if (xlen == 0) xlen = N;
   const int M2 = N / kM1;
   int m2shift = 0;
   while ((1 << m2shift) < M2) ++m2shift;
   switch (Np) {
-    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
-    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
-    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
-    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
-    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode);
+    case 16: return pass1<16>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode, xlen, xoff);
+    case 32: return pass1<32>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode, xlen, xoff);
+    case 64: return pass1<64>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode, xlen, xoff);
+    case 128: return pass1<128>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode, xlen, xoff);
+    case 256: return pass1<256>(x, N, M2, m2shift, win, tabs, T, batch, xbs, tbs, sel, s, y, ymode, xlen, xoff);
     default: return hipErrorInvalidValue;
   }
 }

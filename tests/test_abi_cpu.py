@@ -179,3 +179,13 @@ def test_fam_cross_errors(L):
     assert L.scd_fam_cross_ex(_fake(X), None, 64, 16, 64, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_NULL
     assert L.scd_fam_cross_ex(_fake(X), _fake(X + 0x100000), 64, 16, 2, _fake(W), 0, _fake(O), None) == _lib.SCD_ERR_SIZE
     assert L.scd_fam_cross_ex(_fake(X), _fake(O), 64, 16, 64, _fake(W), 1, _fake(O), None) == _lib.SCD_ERR_ALIAS
+
+
+def test_ssca_block_errors(L):
+    assert L.scd_ssca_block_ex(_fake(X), 8192, 100, 4096, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_block_ex(_fake(X), 8192, 6144, 4096, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_block_ex(_fake(X), (1 << 27) + 64, 0, 4096, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_block_ex(_fake(X), 0, 0, 4096, 64, _fake(W), _fake(O), None) == _lib.SCD_ERR_SIZE
+    o = _lib.ScdOpts()
+    o.precision = _lib.PRECISIONS["split_bf16"]
+    assert L.scd_ssca_block_ex(_fake(X), 8192, 4096, 4096, 64, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
