@@ -13,7 +13,8 @@ otherwise (Stage 2); `per_kernel` gives both kernels both ways. `cpu_baseline` t
 against it. A `fam` object times the FFT accumulation method on the batch workload (16 signals of 16384
 samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes, with `power_form` timing the paper's
 output form (|S|^2 of the kept bins). A `cross` object times the cross SCD of the headline signal and its
-delayed copy.
+delayed copy, and a `stream` object the steady-state time per block of a stream of host blocks (copies
+included).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline] [--no-fam]
                        [--no-cross]
@@ -115,7 +116,7 @@ def main():
     ap.add_argument("--forms", default="fp32,split_bf16,split_fp16,bf16,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fam", action="store_true", help="skip the FAM batch measurement")
-    ap.add_argument("--no-cross", action="store_true", help="skip the cross-SCD measurement")
+    ap.add_argument("--no-cross", action="store_true", help="skip the cross-SCD and streaming measurements")
     ap.add_argument("--mix-signals", type=int, default=8,
                     help="held-out selector-recipe signals for the learned form's mixed-workload line (0: skip)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -256,6 +257,33 @@ def main():
                       "ms_per_step": round(cms, 5), "pts_per_s": round(Np * N / (cms * 1e-3), 1),
                       "speedup_vs_fp32_auto": round(results["fp32"]["ms_per_step"] / cms, 3)}
         del yd
+
+    # Streaming: blocks of 2^20 samples pushed from pinned host memory through SscaReceiver, copy and estimate
+    # overlapped on two streams. The initiation interval includes the host-to-device copies (PCIe), so it is
+    # reported beside `value`, never as it.
+    stream_info = None
+    if "fp32" in forms and not args.no_cross:
+        nblk = 8
+        hx = torch.from_numpy(np.tile(x64, nblk))
+        blocks = []
+        for b in range(nblk):
+            t = torch.empty(N, dtype=torch.complex64, pin_memory=True)
+            t.copy_(hx[b * N:(b + 1) * N])
+            blocks.append(t)
+        for rep in range(2):  # the first pass warms up
+            rx = scd.SscaReceiver(N, Np, nblk * N, dev, win=win)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for t in blocks:
+                rx.push(t)
+            rx.finish()
+            torch.cuda.synchronize()
+            sms = (time.perf_counter() - t0) * 1e3 / nblk
+            del rx
+        stream_info = {"workload": f"{nblk} blocks of N=2^20 from pinned host memory, Np={Np}, neighbouring samples "
+                                   "at block edges (host-to-device copies included)",
+                       "ms_per_block": round(sms, 5), "pts_per_s": round(Np * N / (sms * 1e-3), 1)}
+        del blocks, hx
 
     # Algorithmic HBM bytes and flops per launch (one signal). Pass 1 reads x and writes the intermediate;
     # pass 2 reads and writes Np*N complex values. Flops follow the paper's convention (5 n log2 n per n-point
@@ -408,6 +436,8 @@ def main():
                 **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in li["mix"].items()})
     if cross_info is not None:
         line["cross"] = cross_info
+    if stream_info is not None:
+        line["stream"] = stream_info
     print(json.dumps(line), flush=True)
 
 

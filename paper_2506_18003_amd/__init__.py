@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import PRECISIONS, ScdError  # noqa: F401
 
-__all__ = ["ssca", "ssca_block", "ssca_stream", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_cross", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
+__all__ = ["ssca", "ssca_block", "ssca_stream", "SscaReceiver", "ssca_cross", "ssca_batch", "ssca_stage1", "ssca_stage2", "fam", "fam_cross", "fam_power", "ssca_coords", "fam_coords", "fam_paper_view", "hamming", "ScdError",
            "ssca_workspace_size", "fam_workspace_size", "shutdown", "version"]
 
 _win_cache: dict = {}
@@ -119,6 +119,57 @@ def ssca_stream(x, N: int, Np: int, win=None):
     (ssca_block at offsets 0, N, 2N, ...); yields (offset, S) in order, enqueued on the current stream."""
     for off in range(0, x.shape[-1] - N + 1, N):
         yield off, ssca_block(x, off, N, Np, win=win)
+
+
+class SscaReceiver:
+    """Streaming SSCA of blocks of N samples arriving from the host. Each pushed block (a pinned complex64
+    CPU tensor [N]) is copied into a device buffer sized for `capacity` samples on a copy stream, while the
+    previous block is estimated with scd_ssca_block_ex on the compute stream (ordered by an event), so copy
+    and estimate overlap. A block is estimated once its right neighbour has arrived, so its edge frames read
+    the true samples; finish() estimates the last one (zeros after it). Estimates come back in order as
+    (offset, S [Np, N]) from push() and finish()."""
+
+    def __init__(self, N: int, Np: int, capacity: int, device, win=None):
+        torch = _torch()
+        if capacity % N != 0 or capacity < N:
+            raise ValueError("capacity must be a positive multiple of N")
+        self.N, self.Np, self.device, self.win = N, Np, torch.device(device), win
+        self.buf = torch.zeros(capacity, dtype=torch.complex64, device=self.device)
+        self.copy_stream = torch.cuda.Stream(self.device)  # default priority
+        self.count = 0
+        self._hold = []  # host blocks whose copies may still be in flight (kept alive until finish())
+
+    def _estimate(self, b):
+        N = self.N
+        end = min(self.count, b + 2) * N
+        return b * N, ssca_block(self.buf[:end], b * N, N, self.Np, win=self.win)
+
+    def push(self, block):
+        """Enqueue one host block; returns the estimate of the block before it, or None for the first."""
+        torch = _torch()
+        N = self.N
+        if block.shape != (N,) or block.dtype != torch.complex64 or block.device.type != "cpu":
+            raise ValueError(f"a block is a complex64 CPU tensor of {N} samples")
+        if (self.count + 1) * N > self.buf.numel():
+            raise ValueError("the receiver's buffer is full")
+        b = self.count
+        cur = torch.cuda.current_stream(self.device)
+        # Each block has its own region of the buffer (never reused), so the copy need not wait for estimates.
+        with torch.cuda.stream(self.copy_stream):
+            self.buf[b * N:(b + 1) * N].copy_(block, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(self.copy_stream)
+        self._hold.append(block)
+        self.count += 1
+        cur.wait_event(ev)
+        return self._estimate(b - 1) if b >= 1 else None
+
+    def finish(self):
+        """Estimate the last block (its right edge reads zeros) and wait for every copy."""
+        out = self._estimate(self.count - 1) if self.count else None
+        self.copy_stream.synchronize()
+        self._hold.clear()
+        return out
 
 
 def ssca_cross(x, y, Np: int, win=None, conjugate=False, out=None, workspace=None):

@@ -47,3 +47,24 @@ def test_stream_of_blocks(dev):
         assert np.abs(S.cpu().numpy() - ref).max() <= TOL_FP32 * np.abs(ref).max(), off
         offs.append(off)
     assert offs == [0, 4096, 8192, 12288]
+
+
+def test_receiver_streams_host_blocks(dev):
+    """Blocks pushed from pinned host memory come back, in order, equal bit for bit to ssca_block of the whole
+    signal resident on the device (copy and estimate overlap on two streams)."""
+    N, Np, nb = 4096, 64, 5
+    x = sg.qpsk(nb * N, 0.1, 8, 4.0, sg.rng_for(113, 0)).astype(np.complex64)
+    full = torch.from_numpy(x).to(dev)
+    rx = scd.SscaReceiver(N, Np, nb * N, dev)
+    got = []
+    for b in range(nb):
+        blk = torch.empty(N, dtype=torch.complex64, pin_memory=True)
+        blk.copy_(torch.from_numpy(x[b * N:(b + 1) * N]))
+        r = rx.push(blk)
+        if r is not None:
+            got.append((r[0], r[1].clone()))
+    got.append(rx.finish())
+    torch.cuda.synchronize()
+    assert [o for o, _ in got] == [b * N for b in range(nb)]
+    for off, S in got:
+        assert torch.equal(S, scd.ssca_block(full, off, N, Np)), off
