@@ -359,7 +359,7 @@ def main():
                         fp["win"].astype(np.float32).astype(np.float64))
             fam_line["max_err_vs_oracle_signal0"] = float(np.abs(fout[0].cpu().numpy() - ref).max() / np.abs(ref).max())
         del fout
-        # The paper's output form (|S|^2 over |q_c| < P/4, scd_fam_power_ex): same kernels, a quarter of the
+        # The paper's output form (|S|^2 over -P/4 <= q_c < P/4, scd_fam_power_ex): same kernels, a quarter of the
         # output bytes.
         pout = torch.empty(fB, fNp, fNp, fP // 2, dtype=torch.float32, device=dev)
         for _ in range(args.warmup):

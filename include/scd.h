@@ -175,7 +175,7 @@ int scd_fam(const float* x, int Np, int L, int P, const float* win, float* out);
 int scd_fam_ex(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts);
 
 /* scd_fam_power_ex - the output the paper's FAM keeps (Alg. 1: |S|^2 of the second FFT over its central half,
- * the bins with |q_c| < P/4), written by the FAM kernel itself instead of the complex grid:
+ * the bins with -P/4 <= q_c < P/4), written by the FAM kernel itself instead of the complex grid:
  *   out[k][l][j] = |S[k][l][q]|^2, q = j for j < P/4 and q = j + P/2 for j >= P/4 (j < P/2),
  * each power rounded as re*re + im*im with every operation rounded to FP32 (no fused multiply-add).
  *   out  device, Np*Np*(P/2) floats per signal, row-major [Np][Np][P/2]; opts->out_stride counts floats.

@@ -57,10 +57,21 @@ def acp(x, Np, win):
     return sum(np.abs(O.ssca(s, Np, win)) ** 2 for s in segs)
 
 
+def alpha0_bin(Np, nc):
+    """q0(k) for every strip k of an nc-point SSCA: the bin where alpha = f_k + q_c/nc is zero."""
+    return (-_signed(np.arange(Np), Np) * (nc // Np)) % nc
+
+
+def label_off_mask(k, Np, N):
+    """Bins q of strip k whose cycle frequency alpha = f_k + q_c/N is at least 1/256 away from 0 modulo 1."""
+    q = np.arange(N)
+    return np.abs(_signed((q + _signed(k, Np) * (N // Np)) % N, N)) >= N // ALPHA_GUARD_DIV
+
+
 def features_from_acp(A, Np):
     nc = A.shape[1]
     k = np.arange(Np)
-    q0 = (-_signed(k, Np) * (nc // Np)) % nc
+    q0 = alpha0_bin(Np, nc)
     psd = 0.5 * np.log(A[k, q0] + 1e-30)
     psd = psd - psd.mean()
     out = np.empty(Np)
@@ -79,12 +90,10 @@ def features(x, Np, win):
 
 def labels_from_scd(S):
     Np, N = S.shape
-    q = np.arange(N)
     lab = np.zeros(Np)
     ratio = np.zeros(Np)
     for k in range(Np):
-        kc = _signed(k, Np)
-        off = np.abs(_signed((q + kc * (N // Np)) % N, N)) >= N // ALPHA_GUARD_DIV
+        off = label_off_mask(k, Np, N)
         p = np.abs(S[k, off]) ** 2
         ratio[k] = p.max() / p.mean()
         lab[k] = 1.0 if ratio[k] > T_LABEL else 0.0

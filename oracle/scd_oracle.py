@@ -206,7 +206,7 @@ def fam_coords(Np, L, P):
 
 
 def fam_paper_view(S):
-    """|S|^2 over the central half of the q axis (|q_c| < P/4), in natural order [0..P/4-1, -P/4..-1]."""
+    """|S|^2 over the central half of the q axis (-P/4 <= q_c < P/4), in natural order [0..P/4-1, -P/4..-1]."""
     P = S.shape[-1]
     keep = np.concatenate([np.arange(0, P // 4), np.arange(P - P // 4, P)])
     return np.abs(S[..., keep]) ** 2

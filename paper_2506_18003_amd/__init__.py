@@ -320,7 +320,7 @@ def fam_cross(x, y, Np: int, L: int | None = None, P: int | None = None, win=Non
 
 
 def fam_power(x, Np: int, L: int | None = None, P: int | None = None, win=None, out=None, workspace=None):
-    """The paper's FAM output, |S[k][l][q]|^2 over |q_c| < P/4 ([.., Np, Np, P/2] float32, bins in the order of
+    """The paper's FAM output, |S[k][l][q]|^2 over -P/4 <= q_c < P/4 ([.., Np, Np, P/2] float32, bins in the order of
     fam_paper_view), written by the FAM kernel itself; see scd_fam_power_ex."""
     torch = _torch()
     _check_x(x)
@@ -387,7 +387,7 @@ def fam_coords(Np: int, L: int, P: int):
 
 
 def fam_paper_view(S):
-    """|S|^2 over the central half of the alpha-offset axis (|q_c| < P/4), natural order
+    """|S|^2 over the central half of the alpha-offset axis (-P/4 <= q_c < P/4), natural order
     [0..P/4-1, -P/4..-1]; the bins the paper's FFT2 stage keeps. A view of a complex grid already computed
     (re^2 + im^2, each operation rounded to FP32, as fam_power's kernel computes it)."""
     torch = _torch()

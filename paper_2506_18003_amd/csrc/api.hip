@@ -369,7 +369,7 @@ int scd_ssca_stage2_ex(const float* inter, int64_t N, int Np, float* out, const 
 
 namespace {
 
-// FAM of Eq. (3)-(5); `power` selects the |S|^2 form over |q_c| < P/4 (float output, P/2 bins per pair).
+// FAM of Eq. (3)-(5); `power` selects the |S|^2 form over -P/4 <= q_c < P/4 (float output, P/2 bins per pair).
 int fam_common(const float* x, int Np, int L, int P, const float* win, float* out, const scd_opts* opts,
                bool power, const float* y = nullptr, bool conj = false) {
   if (!x || !win || !out) return fail(SCD_ERR_NULL, "x, win and out must be non-NULL");

@@ -8,7 +8,7 @@
 //   multiplication of Eq. (5)) while loading, takes the P-point DFT of the 16 products in LDS and stores
 //   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic). Row k, which all
 //   16 products share, is staged in LDS once, so each thread's global loads are only its rows l. In the power
-//   form it stores only |S|^2 of the bins the paper keeps after its second FFT (Alg. 1), |q_c| < P/4, in the
+//   form it stores only |S|^2 of the bins the paper keeps after its second FFT (Alg. 1), -P/4 <= q_c < P/4, in the
 //   order q = 0..P/4-1, P-P/4..P-1: a quarter of the complex output's bytes.
 #include <type_traits>
 

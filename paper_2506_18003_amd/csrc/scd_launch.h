@@ -65,7 +65,7 @@ hipError_t launch_ssca_pass2(const float2* T, int N, int Np, const float2* tabs,
                              int64_t tbs, int64_t obs, const SelArg& sel, hipStream_t stream);
 
 // FAM of `batch` signals. x: [batch][P*L] at stride xbs; xt: [batch][Np][P] scratch; out: complex
-// [batch][Np][Np][P], or with `power` float [batch][Np][Np][P/2] (|S|^2 of the bins |q_c| < P/4); obs in elements.
+// [batch][Np][Np][P], or with `power` float [batch][Np][Np][P/2] (|S|^2 of the bins -P/4 <= q_c < P/4); obs in elements.
 // With y (laid out like x) the cross form: xt must then hold 2 * batch * Np * P values (X_T, then Y_T), and conj
 // takes Y_T itself instead of its conjugate.
 hipError_t launch_fam_fp32(const float2* x, int Np, int L, int P, const float* win, const float2* tabs,

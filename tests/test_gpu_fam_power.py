@@ -1,4 +1,4 @@
-"""The FAM power form (scd_fam_power_ex): the kernel's |S|^2 over |q_c| < P/4 equals, bit for bit, the paper's
+"""The FAM power form (scd_fam_power_ex): the kernel's |S|^2 over -P/4 <= q_c < P/4 equals, bit for bit, the paper's
 view taken from the complex grid the same kernels compute, and matches the oracle's view of its FP64 FAM."""
 import numpy as np
 import pytest

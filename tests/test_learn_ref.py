@@ -65,8 +65,9 @@ def test_bf16_round_against_torch_and_ties():
     assert LR.bf16_round(1.0 + 2.0 ** -7) == 1.0 + 2.0 ** -7           # representable
 
 
-def test_labels_pure_noise_all_zero_and_bpsk_has_active_strips():
-    N, Np = 8192, 16
+@pytest.mark.parametrize("N", [4096, 8192])
+def test_labels_pure_noise_all_zero_and_bpsk_has_active_strips(N):
+    Np = 16
     w = sg.hamming(Np)
     lab, ratio = LR.labels_from_scd(O.ssca(sg.noise(N, sg.rng_for(70, 0)), Np, w))
     assert lab.sum() == 0 and ratio.max() < LR.T_LABEL
@@ -100,3 +101,105 @@ def test_acp_equals_sum_of_segment_periodograms():
     for b in range(LR.B_F):
         direct += np.abs(O.ssca(x[b * hop: b * hop + LR.N_C], Np, sg.hamming(Np))) ** 2
     assert np.allclose(A, direct, rtol=1e-12)
+
+
+@pytest.mark.parametrize("Np,nc", [(16, 1024), (64, 1024), (8, 256)])
+def test_alpha0_bin_is_where_the_coordinate_map_puts_alpha_zero(Np, nc):
+    """q0(k) (the PSD bin of the features) is the unique bin of strip k whose cycle frequency, by the
+    coordinate map pinned against the Eq. (2) sums, is zero modulo 1 (alpha = -1 in the Nyquist strip)."""
+    _, a = O.ssca_coords(Np, nc)
+    q0 = LR.alpha0_bin(Np, nc)
+    for k in range(Np):
+        zeros = np.flatnonzero(np.abs(((a[k] + 0.5) % 1.0) - 0.5) < 1e-12)
+        assert zeros.tolist() == [q0[k]], (k, zeros, q0[k])
+
+
+@pytest.mark.parametrize("Np,N", [(16, 4096), (8, 2048)])
+def test_label_guard_is_alpha_distance_from_zero_mod_1(Np, N):
+    """The label's off-guard bins of strip k are exactly the cells whose coordinate-map alpha lies at least
+    1/256 away from 0 modulo 1."""
+    _, a = O.ssca_coords(Np, N)
+    for k in range(Np):
+        aw = ((a[k] + 0.5) % 1.0) - 0.5
+        assert np.array_equal(LR.label_off_mask(k, Np, N), np.abs(aw) >= 1.0 / 256 - 1e-12), k
+
+
+def test_psd_feature_peaks_at_a_tone_channel():
+    """A complex tone at f = 3/16 puts its power in the alpha = 0 cell of strip 3: the PSD feature peaks
+    there, above its neighbours that see it through the window's main lobe (a q0 read at alpha = 2 f_k
+    instead would not see it)."""
+    N, Np = 1 << 14, 16
+    n = np.arange(N)
+    x = np.exp(2j * np.pi * 3 / Np * n) + 0.01 * sg.noise(N, sg.rng_for(73, 0))
+    f = LR.features(x, Np, sg.hamming(Np))
+    assert int(np.argmax(f[:Np])) == 3 and f[3] - np.sort(f[:Np])[-2] > 0.5
+
+
+def _bf16_exact_params(Np, hidden, rng):
+    """Weights and features in {-1, 0, 1}, zero biases: every GEMM input of the forward pass is an integer
+    of magnitude <= 256, so bf16 rounding leaves the forward pass exact."""
+    p = {"W1": rng.integers(-1, 2, (hidden, 2 * Np)).astype(float), "b1": np.zeros(hidden),
+         "W2": rng.integers(-1, 2, (hidden, hidden)).astype(float), "b2": np.zeros(hidden),
+         "W3": rng.integers(-1, 2, (Np, hidden)).astype(float), "b3": np.zeros(Np)}
+    return p
+
+
+def test_bf16_forward_rounds_only_gemm_inputs():
+    """With bf16-exact inputs and activations the bf16 forward equals the FP64 forward bit for bit; with
+    general inputs it differs, by no more than the bf16 unit roundoff 2^-8 per rounded GEMM operand."""
+    rng = np.random.default_rng(5)
+    Np, hidden, B = 4, 8, 6
+    p = _bf16_exact_params(Np, hidden, rng)
+    F = rng.integers(-1, 2, (B, 2 * Np)).astype(float)
+    c64, c16 = LR.mlp_forward(p, F), LR.mlp_forward(p, F, bf16=True)
+    for k in ("a1", "a2", "z", "s"):
+        assert np.array_equal(c64[k], c16[k]), k
+    p = _small_params(Np, hidden)
+    F = rng.standard_normal((B, 2 * Np))
+    c64, c16 = LR.mlp_forward(p, F), LR.mlp_forward(p, F, bf16=True)
+    scale = np.abs(F) @ np.abs(p["W1"]).T
+    d = np.abs(c16["a1"] - c64["a1"])
+    assert 0 < d.max() and np.all(d <= 2.01 * 2.0 ** -8 * scale)
+
+
+def _backward_scale(p, F, cache):
+    """Element-wise size of every gradient's terms: the backward pass run on absolute values."""
+    B, Np = cache["s"].shape
+    adz = np.abs(cache["s"]) / (B * Np) + 1.0 / (B * Np)
+    m2, m1 = (cache["a2"] > 0), (cache["a1"] > 0)
+    g = {"W3": adz.T @ np.abs(cache["h2"])}
+    dh2 = adz @ np.abs(p["W3"])
+    g["W2"] = (dh2 * m2).T @ np.abs(cache["h1"])
+    dh1 = (dh2 * m2) @ np.abs(p["W2"])
+    g["W1"] = (dh1 * m1).T @ np.abs(F)
+    g["F"] = (dh1 * m1) @ np.abs(p["W1"])
+    return g
+
+
+def test_bf16_backward_within_rounding_bound_of_exact_backward():
+    """The bf16 backward (the GPU kernels' comparator) rounds the operands of every backward GEMM. On the same
+    forward cache it must equal the exact backward (itself pinned by central differences) within the error
+    those roundings allow: each term carries at most two rounded factors per GEMM, and the error compounds
+    over at most three layers, so |g16 - g64| <= 8 * 2^-8 * (the same backward on absolute values). A
+    transposed weight or a mask taken from the wrong layer breaks that bound."""
+    rng = np.random.default_rng(6)
+    Np, hidden, B = 4, 8, 5
+    p = _small_params(Np, hidden, seed=3)
+    F = rng.standard_normal((B, 2 * Np))
+    y = (rng.random((B, Np)) > 0.5).astype(float)
+    cache = LR.mlp_forward(p, F, bf16=True)
+    g16 = LR.mlp_backward(p, F, y, cache, bf16=True)
+    g64 = LR.mlp_backward(p, F, y, cache, bf16=False)
+    sc = _backward_scale(p, F, cache)
+    bound = 8 * 2.0 ** -8
+    for k in ("W3", "W2", "W1", "F"):
+        d = np.abs(g16[k] - g64[k])
+        assert d.max() > 0, k
+        assert np.all(d <= bound * sc[k] + 1e-300), (k, (d / sc[k]).max())
+    # Planted mistakes in an exact backward, each of which the bound catches.
+    dz = (cache["s"] - y) / (B * Np)
+    da2 = (dz @ p["W3"]) * (cache["a2"] > 0)
+    wrong_t = ((da2 @ p["W2"].T) * (cache["a1"] > 0)).T @ F
+    wrong_mask = ((da2 @ p["W2"]) * (cache["a2"] > 0)).T @ F
+    for wrong in (wrong_t, wrong_mask):
+        assert np.any(np.abs(wrong - g16["W1"]) > bound * sc["W1"])

@@ -311,3 +311,47 @@ def test_coordinate_map_matches_brute_force_frequencies():
             assert abs(((f1 - k / Np) + 0.5) % 1.0 - 0.5) < 1e-12
             assert abs(((f2 + q / N) + 0.5) % 1.0 - 0.5) < 1e-12
             assert -0.5 <= f[k, q] <= 0.5 and -1.0 <= a[k, q] <= 1.0
+
+
+def test_fam_paper_view_is_alg1_write_order():
+    """Alg. 1 writes |z_fft|^2 at indices P/2..3P/4-1, then P/4..P/2-1, of the P-point spectrum read in
+    centred (fftshifted) order, i.e. q_c = 0..P/4-1 followed by q_c = -P/4..-1. The oracle's view must
+    be exactly that, taken here through numpy's fftshift rather than the view's own index list; a view
+    shifted by one bin does not match. The kept set is q_c in [-P/4, P/4)."""
+    x = _sig(256, 21)
+    Np, L, P = 16, 4, 64
+    S = O.fam(x, Np, L, P, sg.hamming(Np))
+    z_abs = np.abs(np.fft.fftshift(S, axes=-1)) ** 2
+    written = np.concatenate([z_abs[..., P // 2:3 * P // 4], z_abs[..., P // 4:P // 2]], axis=-1)
+    assert np.array_equal(O.fam_paper_view(S), written)
+    shifted = np.abs(S[..., np.r_[1:P // 4 + 1, P - P // 4 + 1:P, 0]]) ** 2
+    assert not np.allclose(shifted, written)
+    # The kept bins are the ones inside the channel pair's overlap, |alpha - (f_k - f_l)| <= 1/(4L).
+    _, a = O.fam_coords(Np, L, P)
+    fk = (((np.arange(Np) + Np // 2) % Np) - Np // 2) / Np
+    off = a - (fk[:, None] - fk[None, :])[:, :, None]
+    kept = np.abs(np.fft.fftshift(off, axes=-1))[..., P // 4:3 * P // 4]
+    assert kept.max() <= 1.0 / (4 * L) and np.abs(off).max() > 1.0 / (4 * L)
+
+
+@pytest.mark.parametrize("ka,kb,qd", [(1, 6, 3), (6, 1, -5), (3, 5, 2), (0, 7, -1)])
+def test_fam_coords_place_a_two_tone_cycle_frequency(ka, kb, qd):
+    """Two complex tones at f_a = k_a/Np and f_b = k_b/Np + q_d/(P L) have one cycle frequency
+    alpha = f_a - f_b (the product x_a conj(x_b)). The Eq. (1)/(5) direct sums of the channel pair (k_a, k_b)
+    peak at the bin q whose fam_coords alpha is exactly f_a - f_b (pins the sign of alpha, which operand is
+    conjugated, and the spacing 1/(P L)); the cell's f lies within one channel width of (f_a + f_b)/2."""
+    Np, L, P = 8, 2, 32
+    N = P * L
+    n = np.arange(N)
+    sgn = lambda k: ((k + Np // 2) % Np) - Np // 2
+    fa = sgn(ka) / Np
+    fb = sgn(kb) / Np + qd / (P * L)
+    x = np.exp(2j * np.pi * fa * n) + np.exp(2j * np.pi * fb * n)
+    w = list(sg.hamming(Np))
+    row = np.array([B.fam_cell_eq15(x, w, L, P, ka, kb, q) for q in range(P)])
+    q = int(np.argmax(np.abs(row)))
+    f, a = O.fam_coords(Np, L, P)
+    assert abs(a[ka, kb, q] - (fa - fb)) < 1e-12
+    assert abs(f[ka, kb, q] - (fa + fb) / 2) <= 1.0 / Np
+    # A sign-flipped map (alpha = f_l - f_k - q_c/(P L)) places the same peak at -(f_a - f_b).
+    assert abs(-a[ka, kb, q] - (fa - fb)) > 1e-6
