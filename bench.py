@@ -5,22 +5,25 @@ rotation) and Stage 2 (M2-point DFT), exactly the kernels scd_ssca runs, called 
 HIP events on the launch stream time each kernel inside the timed region.
 
 Prints one JSON line. `value` is SCD points/s = Np*N / (seconds per step) with x, window and output already
-resident in HBM. `roofline` reports the dominant kernel (longest average event-timed duration) against the
-ceiling its arithmetic intensity puts it under: algorithmic flops against the 78.6 TFLOP/s FP32 vector peak
-when flops per algorithmic HBM byte exceed the ridge point (Stage 1), algorithmic HBM bytes against 8 TB/s
-otherwise (Stage 2); `per_kernel` gives both kernels both ways. `cpu_baseline` times the FP64 oracle on this host
-(single-threaded numpy) over all 64 strips of the same signal, which also gives the error of every GPU form
-against it. A `fam` object times the FFT accumulation method on the batch workload (16 signals of 16384
-samples, Np = 256, L = 64, P = 256) against its algorithmic HBM bytes, with `power_form` timing the paper's
-output form (|S|^2 of the kept bins). A `cross` object times the cross SCD of the headline signal and its
-delayed copy, and a `stream` object the steady-state time per block of a stream of host blocks (copies
-included).
+resident in HBM. `roofline` reports the dominant kernel (longest average event-timed duration) against the HBM
+roofline: its algorithmic bytes per launch over its average duration, against 8 TB/s; `B_2p_frac` and
+`B_min_frac` give the whole step against the two byte models (x + output + one round trip of the intermediate,
+and x + output), `alu` the dominant kernel's paper-convention flops against the FP32 vector peak, and
+`per_kernel` both kernels both ways. `cpu_baseline` times the FP64 oracle on this host over all 64 strips of the
+same signal, on every core of the host's share (a process pool over strips) and on one core; the oracle's
+result also gives the error of every GPU form. A `fam` object times the FFT accumulation method on the batch
+workload (16 signals of 16384 samples, Np = 256, L = 64, P = 256), a `fam_paper` object on the paper's own
+FAM workload (N = 2048, Np = 256, L = 64, P = 32) as ms per estimate and input samples per second, both in
+complex and power form. A `cross` object times the cross SCD of the headline signal and its delayed copy, and
+a `stream` object the steady-state time per block of a stream of host blocks (copies included).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline] [--no-fam]
-                       [--no-cross]
+                       [--no-cross] [--cpu-workers W]
        python bench.py --write-traffic FETCH_CSV WRITE_CSV   (no GPU: summarise two rocprofv3 --pmc runs of
        `bench.py --copy-calib --forms fp32`, one with FETCH_SIZE and one with WRITE_SIZE, into the committed
        per-launch HBM traffic of the SSCA kernels)
+       python bench.py --counter-table CSV [CSV ...]   (no GPU: per-kernel averages of rocprofv3 --pmc counter
+       CSVs as a markdown table)
 """
 from __future__ import annotations
 
@@ -38,8 +41,9 @@ if ROOT not in sys.path:
 METRIC = "SCD pts/s, SSCA N=2^20 N'=64: FP32 vs split-BF16 vs learned strips"
 PAPER_PTS_PER_S = 2 ** 26 / 0.114  # VCK5000, 114 ms per SSCA estimate at N=2^20, N_P=64 (Table III)
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (the library is built without them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32 instructions)
+# What the library's code can reach: it is built without packed FP32 instructions, so one FMA per lane and
+# cycle: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 KERNEL_SOURCES = ("scd_device.h", "scd_launch.h", "ssca_fp32.hip")  # the FP32 SSCA kernels
 
@@ -66,7 +70,7 @@ def measured_traffic(kernel: str, digest: str):
 
 
 CALIB_BYTES = 256 << 20          # the --copy-calib kernel reads and writes this many bytes
-TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32<64, true, false, true, 0>", "ssca_pass2": "ssca_pass2_fp32"}
+TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32<64, true, false, false, 0>", "ssca_pass2": "ssca_pass2_fp32"}
 
 
 def write_traffic(fetch_csv: str, write_csv: str) -> dict:
@@ -105,9 +109,62 @@ def write_traffic(fetch_csv: str, write_csv: str) -> dict:
     return out
 
 
+def counter_table(paths) -> str:
+    """Markdown table of per-kernel average counter values (one row per kernel and counter) from rocprofv3
+    --pmc CSVs."""
+    import csv
+
+    acc = {}
+    for path in paths:
+        for row in csv.DictReader(open(path)):
+            acc.setdefault(row["Kernel_Name"], {}).setdefault(row["Counter_Name"], []).append(
+                float(row["Counter_Value"]))
+    lines = ["| kernel | counter | dispatches | average per dispatch |", "|---|---|---|---|"]
+    for k in sorted(acc):
+        short = k.split("(")[0].replace("void ", "").replace("scd::(anonymous namespace)::", "")
+        for c in sorted(acc[k]):
+            v = acc[k][c]
+            lines.append(f"| {short} | {c} | {len(v)} | {sum(v) / len(v):.6g} |")
+    return "\n".join(lines)
+
+
+def _oracle_strips(args):
+    """Pool worker: FP64 oracle strips ks of the signal (the product path never calls this)."""
+    x, Np, w, ks = args
+    from oracle import scd_oracle as O
+
+    return ks, [O.ssca_strip(x, Np, w, k) for k in ks]
+
+
+def cpu_oracle_ssca(x, Np, w, workers):
+    """All Np strips of the FP64 oracle SSCA: in this process (workers == 1) or on a process pool over strips.
+    Returns (S, seconds)."""
+    import numpy as np
+
+    t0 = time.perf_counter()
+    if workers == 1:
+        from oracle import scd_oracle as O
+
+        S = np.stack([O.ssca_strip(x, Np, w, k) for k in range(Np)])
+        return S, time.perf_counter() - t0
+    import multiprocessing as mp
+
+    chunks = [list(range(i, Np, workers)) for i in range(workers)]
+    S = np.empty((Np, len(x)), np.complex128)
+    # Spawned workers start a fresh interpreter: they never inherit this process's GPU context.
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for ks, rows in pool.imap_unordered(_oracle_strips, [(x, Np, w, ks) for ks in chunks]):
+            for k, r in zip(ks, rows):
+                S[k] = r
+    return S, time.perf_counter() - t0
+
+
 def main():
     if len(sys.argv) == 4 and sys.argv[1] == "--write-traffic":
         write_traffic(sys.argv[2], sys.argv[3])
+        return
+    if len(sys.argv) >= 3 and sys.argv[1] == "--counter-table":
+        print(counter_table(sys.argv[2:]))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +176,8 @@ def main():
     ap.add_argument("--no-cross", action="store_true", help="skip the cross-SCD and streaming measurements")
     ap.add_argument("--mix-signals", type=int, default=8,
                     help="held-out selector-recipe signals for the learned form's mixed-workload line (0: skip)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes for the oracle's all-core leg (0: min(16, os.cpu_count()), the host share of one GPU)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 256 MiB read + 256 MiB write elementwise kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -154,6 +213,8 @@ def main():
         del src, dst
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if "learned" in forms and "fp32" not in forms:
+        forms.insert(0, "fp32")  # the learned form is reported as a speedup over the plain FP32 path
     results = {}
     learned_info = None
     if "learned" in forms:
@@ -300,28 +361,26 @@ def main():
     r = results[main_form]
     digest = source_digest()
     kern = {"ssca_pass1": (b1, f1, r["pass1_ms"]), "ssca_pass2": (b2, f2, r["pass2_ms"])}
-    ridge = VALU_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS  # flop/byte where the two ceilings meet
 
     def kernel_roof(name):
+        """The kernel's algorithmic HBM bytes over its average duration against the 8 TB/s peak, and its
+        paper-convention flops against the FP32 vector peaks (secondary)."""
         nb, nf, ms = kern[name]
-        if nf / nb > ridge:  # compute side of the roofline: FP32 vector ALU
-            ach = nf / (ms * 1e-3) / 1e12
-            return {"bound": "alu", "achieved": round(ach, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / VALU_PEAK_TFLOPS, 4)}
-        ach = nb / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4)}
+        gbs = nb / (ms * 1e-3) / 1e9
+        tfs = nf / (ms * 1e-3) / 1e12
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_ms": round(ms, 5), "algorithmic_bytes": nb,
+                "alu": {"achieved": round(tfs, 2), "unit": "TFLOP/s", "algorithmic_flops": nf,
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "frac": round(tfs / FP32_VECTOR_PEAK_TFLOPS, 4),
+                        "peak_without_packed_fp32": VALU_PEAK_TFLOPS,
+                        "frac_without_packed_fp32": round(tfs / VALU_PEAK_TFLOPS, 4)}}
 
     dom = max(kern, key=lambda k: kern[k][2])
-    roof = dict(kernel_roof(dom), kernel=dom, traffic=measured_traffic(dom, digest),
-                algorithmic_bytes=kern[dom][0], algorithmic_flops=kern[dom][1], avg_ms=round(kern[dom][2], 5))
+    roof = dict(kernel_roof(dom), kernel=dom, traffic=measured_traffic(dom, digest))
     roof.update({
-            "per_kernel": {k: dict(kernel_roof(k), avg_ms=round(v[2], 5), algorithmic_bytes=v[0],
-                                   algorithmic_flops=v[1], hbm_GBs=round(v[0] / (v[2] * 1e-3) / 1e9, 1),
-                                   hbm_frac=round(v[0] / (v[2] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
-                           for k, v in kern.items()},
             "B_2p_frac": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "per_kernel": {k: kernel_roof(k) for k in kern},
             "source_digest": digest})
 
     fam_line = None
@@ -382,16 +441,19 @@ def main():
     cpu = None
     errs = {}
     if not args.no_cpu_baseline:
-        from oracle import scd_oracle as O
-
+        # The FP64 oracle (per-strip FIR channelizer + numpy.fft) over all 64 strips of the same signal: once on
+        # a process pool over strips using the host's share of cores, once on a single core.
+        ncpu = os.cpu_count() or 1
+        workers = args.cpu_workers or max(1, min(16, ncpu))
         xf = x64.astype(np.complex128)
         wf = w32.astype(np.float64)
-        t0 = time.perf_counter()
-        ref = np.stack([O.ssca_strip(xf, Np, wf, k) for k in range(Np)])
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(Np * N / dt, 1), "unit": "SCD pts/s", "cores": 1, "kind": "oracle",
-               "sample": f"all {Np} strips of the same N=2^20 signal (FP64 numpy oracle: per-strip FIR "
-                         f"channelizer + numpy.fft), {dt:.1f} s single-threaded"}
+        ref, dt_all = cpu_oracle_ssca(xf, Np, wf, workers)
+        _, dt_one = cpu_oracle_ssca(xf, Np, wf, 1)
+        cpu = {"value": round(Np * N / dt_all, 1), "unit": "SCD pts/s", "cores": workers, "kind": "oracle",
+               "sample": f"all {Np} strips of the same N=2^20 signal (FP64 numpy oracle: per-strip FIR channelizer "
+                         f"+ numpy.fft) on a pool of {workers} processes over strips, {dt_all:.2f} s",
+               "os_cpu_count": ncpu, "workers": workers, "seconds": round(dt_all, 3),
+               "single_core": {"value": round(Np * N / dt_one, 1), "cores": 1, "seconds": round(dt_one, 3)}}
         peak = np.abs(ref).max()
         for form, rr in results.items():
             errs[form] = float(np.abs(rr["out"] - ref).max() / peak)

@@ -33,6 +33,7 @@ constexpr int kHalfSeqs = 32;         // 8 channels x 4 residues per LDS exchang
 constexpr int kXchgFloats = kHalfSeqs * kSeqStride;
 constexpr int kP2Threads = 256;
 constexpr int kPairMinBlocks = 256;   // paired Stage-1 grids at least this large (one block per CU)
+constexpr int kSingleMinBlocks = 2048;  // single-subset grids this large fill two blocks per CU for four rounds
 
 // omega_N^a for 0 <= a < N from the two-level table: omega_N^{a mod 1024} * omega_1024^{(a / 1024) * 1024 / M2}.
 __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
@@ -358,9 +359,13 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
                  const float2* y, int ymode, int xlen, int xoff) {
   if (sel.nsub <= 0) return hipSuccess;
   if (ymode != 0 && sel.dev) return hipErrorInvalidValue;  // the cross forms run on every strip
-  // Subset pairs halve the x traffic and the fold work per strip; they are used when the paired grid still
-  // gives every CU a workgroup (otherwise, e.g. for short segments, twice as many single-subset workgroups
-  // finish sooner).
+  // Subset pairs halve the x traffic and the fold work per strip, but a paired workgroup holds 256 KB of
+  // channel values and fills a CU alone, so every CU computes and then stores its intermediate in step with the
+  // others and the stores hardly overlap any arithmetic (at N = 2^20, Np = 64: 0.243 ms, of which 0.100 ms
+  // comes back when the stores are left out). Two single-subset workgroups share a CU and overlap one's stores
+  // with the other's arithmetic (0.216 ms, 0.033 ms of it stores), which outweighs the extra fold work once the
+  // single-subset grid fills the GPU for several rounds. Pairs serve the grids in between, and grids too small to
+  // give every CU a paired workgroup (e.g. short segments) run single subsets.
   auto go = [&](auto kern, bool pair) {
     dim3 grid(M2 * (pair ? sel.npair : sel.nsub), batch);
     hipLaunchKernelGGL(kern, grid, dim3((pair ? 2 : 1) * kP1Threads), 0, s, x, y, N, xlen, xoff, M2, m2shift, win,
@@ -379,7 +384,9 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
     else launch_phase(pair_tag, std::false_type{});
   };
   if constexpr (NP >= 32) {
-    if (static_cast<int64_t>(M2) * sel.npair * batch >= kPairMinBlocks) launch(std::true_type{});
+    const int64_t single_blocks = static_cast<int64_t>(M2) * sel.nsub * batch;
+    const int64_t pair_blocks = static_cast<int64_t>(M2) * sel.npair * batch;
+    if (single_blocks < kSingleMinBlocks && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
     else launch(std::false_type{});
   } else {
     launch(std::false_type{});
