@@ -221,6 +221,42 @@ typedef struct scd_selector {
   float conf_min;      /* fall back to the full SSCA when min_k max(s_k, 1 - s_k) < conf_min */
 } scd_selector;
 
+/* A library-owned selector: the packed MLP parameters, feature means and scales in device memory of the device
+ * that was current when it was created, with the score threshold and confidence floor. Opaque; the calls below
+ * create, save, load and free it, and scd_model_selector gives the scd_selector view scd_ssca_learned takes.
+ * Model files are little-endian: "SCDM", u32 version 1, i32 Np, i32 parameter count, f32 theta, f32 conf_min,
+ * the parameters, mu (2 Np) and sigma (2 Np) as f32, then a u32 FNV-1a hash of every preceding byte. */
+typedef struct scd_model scd_model;
+
+/* Create a model from HOST arrays (params: scd_mlp_param_count(Np) floats, mu and sigma: 2 Np floats each), which
+ * are copied to device memory. Every value must be finite, sigma positive, theta and conf_min in [0, 1].
+ * *model is NULL on error. Errors: SCD_ERR_NULL, SCD_ERR_SIZE (Np), SCD_ERR_MODEL (values), SCD_ERR_NOMEM,
+ * SCD_ERR_HIP. */
+int scd_model_create(int Np, const float* params, const float* mu, const float* sigma, float theta, float conf_min,
+                     scd_model** model);
+
+/* Free a model (NULL is a no-op). A model must not be freed while work that reads it is queued. */
+int scd_model_destroy(scd_model* model);
+
+/* The scd_selector view of a model (device pointers owned by the model, valid until scd_model_destroy). */
+int scd_model_selector(const scd_model* model, scd_selector* selector);
+
+/* Copy a model's arrays to HOST memory (any pointer may be NULL to skip that array); waits for the device. */
+int scd_model_read(const scd_model* model, float* params, float* mu, float* sigma);
+
+/* Write a model file from HOST arrays, without a device (the checks of scd_model_create apply). Errors:
+ * SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_MODEL (values, or the file cannot be written). */
+int scd_model_write(const char* path, int Np, const float* params, const float* mu, const float* sigma, float theta,
+                    float conf_min);
+
+/* Write a model to a file (scd_model_read, then scd_model_write). */
+int scd_model_save(const scd_model* model, const char* path);
+
+/* Read and check a model file (magic, version, Np, size, hash and values, all before any device call), then
+ * create the model on the current device. Errors: SCD_ERR_NULL, SCD_ERR_MODEL (missing, malformed or corrupt
+ * file), and those of scd_model_create. */
+int scd_model_load(const char* path, scd_model** model);
+
 /* Number of packed MLP parameters for Np channels (262912 for Np = 256), or SCD_ERR_SIZE. */
 int scd_mlp_param_count(int Np);
 

@@ -102,6 +102,14 @@ _SIGS = {
     "scd_ssca_learned": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ScdOpts)]),
     "scd_ssca_batch": (ctypes.c_int, [ctypes.POINTER(ScdSscaItem), ctypes.c_int, ctypes.POINTER(ScdOpts)]),
+    "scd_model_create": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "scd_model_destroy": (ctypes.c_int, [_P]),
+    "scd_model_selector": (ctypes.c_int, [_P, ctypes.POINTER(ScdSelector)]),
+    "scd_model_read": (ctypes.c_int, [_P, _P, _P, _P]),
+    "scd_model_write": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _P, _P, _P, ctypes.c_float, ctypes.c_float]),
+    "scd_model_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "scd_model_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
     "scd_set_stream": (ctypes.c_int, [_P]),
     "scd_last_error": (ctypes.c_char_p, []),
     "scd_version": (ctypes.c_int, []),

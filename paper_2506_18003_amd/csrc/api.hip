@@ -3,6 +3,7 @@
 // checks arguments and enqueues launches.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
@@ -424,6 +425,198 @@ int fam_common(const float* x, int Np, int L, int P, const float* win, float* ou
 }
 
 }  // namespace
+
+// ---- selector model lifecycle ----------------------------------------------------------------------------
+// A model owns one device block [params | mu | sigma] on the device that was current at creation. Model files
+// are little-endian: "SCDM", u32 version 1, i32 Np, i32 parameter count, f32 theta, f32 conf_min, the
+// parameters, mu (2 Np) and sigma (2 Np) as f32, and a u32 FNV-1a hash of every byte before it.
+struct scd_model {
+  int device;
+  int Np;
+  int nparams;
+  float theta, conf_min;
+  float* block;  // device: params (16-byte aligned at the block start), mu, sigma
+};
+
+namespace {
+
+constexpr char kModelMagic[4] = {'S', 'C', 'D', 'M'};
+constexpr uint32_t kModelVersion = 1;
+constexpr size_t kModelHeader = 4 + 4 + 4 + 4 + 4 + 4;
+
+uint32_t fnv1a(const unsigned char* p, size_t n) {
+  uint32_t h = 2166136261u;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 16777619u;
+  }
+  return h;
+}
+
+// Host-side checks shared by creation, writing and loading.
+int check_model_values(int Np, const float* params, const float* mu, const float* sigma, float theta, float conf_min) {
+  const int n = scd_mlp_param_count(Np);
+  if (n < 0) return fail(SCD_ERR_SIZE, "model Np = %d must be a power of two in [16, 256]", Np);
+  if (!(theta >= 0.f && theta <= 1.f)) return fail(SCD_ERR_MODEL, "theta = %g must lie in [0, 1]", theta);
+  if (!(conf_min >= 0.f && conf_min <= 1.f)) return fail(SCD_ERR_MODEL, "conf_min = %g must lie in [0, 1]", conf_min);
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return fail(SCD_ERR_MODEL, "parameter %d is not finite", i);
+  for (int i = 0; i < 2 * Np; ++i) {
+    if (!std::isfinite(mu[i])) return fail(SCD_ERR_MODEL, "mu[%d] is not finite", i);
+    if (!(std::isfinite(sigma[i]) && sigma[i] > 0.f)) return fail(SCD_ERR_MODEL, "sigma[%d] must be positive", i);
+  }
+  return SCD_OK;
+}
+
+template <class T>
+void put(std::string& b, T v) {
+  b.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+int scd_model_write(const char* path, int Np, const float* params, const float* mu, const float* sigma, float theta,
+                    float conf_min) {
+  if (!path || !params || !mu || !sigma) return fail(SCD_ERR_NULL, "NULL argument");
+  int rc;
+  if ((rc = check_model_values(Np, params, mu, sigma, theta, conf_min))) return rc;
+  const int n = scd_mlp_param_count(Np);
+  std::string b;
+  b.reserve(kModelHeader + 4u * (n + 4 * Np) + 4);
+  b.append(kModelMagic, 4);
+  put<uint32_t>(b, kModelVersion);
+  put<int32_t>(b, Np);
+  put<int32_t>(b, n);
+  put<float>(b, theta);
+  put<float>(b, conf_min);
+  b.append(reinterpret_cast<const char*>(params), 4u * n);
+  b.append(reinterpret_cast<const char*>(mu), 8u * Np);
+  b.append(reinterpret_cast<const char*>(sigma), 8u * Np);
+  put<uint32_t>(b, fnv1a(reinterpret_cast<const unsigned char*>(b.data()), b.size()));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SCD_ERR_MODEL, "cannot open %s for writing", path);
+  const size_t w = std::fwrite(b.data(), 1, b.size(), f);
+  const int closed = std::fclose(f);
+  if (w != b.size() || closed != 0) return fail(SCD_ERR_MODEL, "writing %s failed", path);
+  return SCD_OK;
+}
+
+int scd_model_create(int Np, const float* params, const float* mu, const float* sigma, float theta, float conf_min,
+                     scd_model** model) {
+  if (!model) return fail(SCD_ERR_NULL, "NULL model handle");
+  *model = nullptr;
+  if (!params || !mu || !sigma) return fail(SCD_ERR_NULL, "NULL argument");
+  int rc;
+  if ((rc = check_model_values(Np, params, mu, sigma, theta, conf_min))) return rc;
+  const int n = scd_mlp_param_count(Np);
+  int dev;
+  if ((rc = current_device(&dev))) return rc;
+  float* block = nullptr;
+  const size_t bytes = 4u * (static_cast<size_t>(n) + 4u * Np);
+  hipError_t e = hipMalloc(&block, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SCD_ERR_NOMEM, "model allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  e = hipMemcpy(block, params, 4u * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(block + n, mu, 8u * Np, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(block + n + 2 * Np, sigma, 8u * Np, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(block);
+    return hip_fail(e, "model upload");
+  }
+  *model = new scd_model{dev, Np, n, theta, conf_min, block};
+  return SCD_OK;
+}
+
+int scd_model_destroy(scd_model* model) {
+  if (!model) return SCD_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(model->device);
+  const hipError_t e = hipFree(model->block);
+  (void)hipSetDevice(cur);
+  delete model;
+  if (e != hipSuccess) return hip_fail(e, "model free");
+  return SCD_OK;
+}
+
+int scd_model_selector(const scd_model* model, scd_selector* selector) {
+  if (!model || !selector) return fail(SCD_ERR_NULL, "NULL argument");
+  selector->Np = model->Np;
+  selector->params = model->block;
+  selector->mu = model->block + model->nparams;
+  selector->sigma = model->block + model->nparams + 2 * model->Np;
+  selector->theta = model->theta;
+  selector->conf_min = model->conf_min;
+  return SCD_OK;
+}
+
+int scd_model_read(const scd_model* model, float* params, float* mu, float* sigma) {
+  if (!model) return fail(SCD_ERR_NULL, "NULL model");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  hipError_t e = hipSetDevice(model->device);
+  if (e == hipSuccess && params) e = hipMemcpy(params, model->block, 4u * model->nparams, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && mu) e = hipMemcpy(mu, model->block + model->nparams, 8u * model->Np, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && sigma)
+    e = hipMemcpy(sigma, model->block + model->nparams + 2 * model->Np, 8u * model->Np, hipMemcpyDeviceToHost);
+  (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hip_fail(e, "model read-back");
+  return SCD_OK;
+}
+
+int scd_model_save(const scd_model* model, const char* path) {
+  if (!model || !path) return fail(SCD_ERR_NULL, "NULL argument");
+  std::string host(4u * (static_cast<size_t>(model->nparams) + 4u * model->Np), '\0');
+  float* h = reinterpret_cast<float*>(&host[0]);
+  int rc;
+  if ((rc = scd_model_read(model, h, h + model->nparams, h + model->nparams + 2 * model->Np))) return rc;
+  return scd_model_write(path, model->Np, h, h + model->nparams, h + model->nparams + 2 * model->Np, model->theta,
+                         model->conf_min);
+}
+
+int scd_model_load(const char* path, scd_model** model) {
+  if (!path || !model) return fail(SCD_ERR_NULL, "NULL argument");
+  *model = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SCD_ERR_MODEL, "cannot open %s", path);
+  std::string b;
+  char chunk[1 << 16];
+  size_t r;
+  while ((r = std::fread(chunk, 1, sizeof(chunk), f)) > 0) {
+    b.append(chunk, r);
+    if (b.size() > (64u << 20)) break;
+  }
+  std::fclose(f);
+  if (b.size() < kModelHeader + 4) return fail(SCD_ERR_MODEL, "%s: too short for a model file", path);
+  if (std::memcmp(b.data(), kModelMagic, 4) != 0) return fail(SCD_ERR_MODEL, "%s: not a model file", path);
+  uint32_t version;
+  int32_t Np, n;
+  float theta, conf_min;
+  std::memcpy(&version, b.data() + 4, 4);
+  std::memcpy(&Np, b.data() + 8, 4);
+  std::memcpy(&n, b.data() + 12, 4);
+  std::memcpy(&theta, b.data() + 16, 4);
+  std::memcpy(&conf_min, b.data() + 20, 4);
+  if (version != kModelVersion) return fail(SCD_ERR_MODEL, "%s: model file version %u is not %u", path, version, kModelVersion);
+  const int expect = scd_mlp_param_count(Np);
+  if (expect < 0) return fail(SCD_ERR_MODEL, "%s: Np = %d is not supported", path, Np);
+  if (n != expect) return fail(SCD_ERR_MODEL, "%s: %d parameters, %d expected for Np = %d", path, n, expect, Np);
+  const size_t want = kModelHeader + 4u * (static_cast<size_t>(n) + 4u * Np) + 4;
+  if (b.size() != want) return fail(SCD_ERR_MODEL, "%s: %zu bytes, %zu expected", path, b.size(), want);
+  uint32_t hash;
+  std::memcpy(&hash, b.data() + want - 4, 4);
+  if (hash != fnv1a(reinterpret_cast<const unsigned char*>(b.data()), want - 4))
+    return fail(SCD_ERR_MODEL, "%s: checksum mismatch", path);
+  std::string arr = b.substr(kModelHeader, want - 4 - kModelHeader);  // aligned copy of the arrays
+  const float* h = reinterpret_cast<const float*>(arr.data());
+  return scd_model_create(Np, h, h + n, h + n + 2 * Np, theta, conf_min, model);
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -45,6 +45,21 @@ __device__ __forceinline__ float2 load_c64(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<unsigned>(idx) * 8u, 0, 0));
 }
 
+// Raw buffer resource over `bytes` bytes (up to 4 GiB - 1) for stores: 8-byte stores at a per-lane byte offset
+// voff plus a wave-uniform byte offset soff. Splitting the address this way keeps the per-store address
+// arithmetic out of the vector ALU: a loop-invariant voff per lane, and soff (a compile-time multiple of a
+// kernel argument) in a scalar register.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_u(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+typedef unsigned int v2u_t __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ void store_c64(__amdgpu_buffer_rsrc_t r, float2 v, unsigned voff, unsigned soff) {
+  // Cache policy bit 1 is the nontemporal hint on gfx950.
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u_t, v), r, static_cast<int>(voff),
+                                        static_cast<int>(soff), NT ? 2 : 0);
+}
+
 // Streaming (nontemporal) 16-byte global accesses of two adjacent complex values.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void ld2_nt(const float2* p, float2& a, float2& b) {

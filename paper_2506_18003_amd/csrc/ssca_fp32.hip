@@ -99,6 +99,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   const int c = cg + half * (S / 2);  // this thread's subset
   x += blockIdx.y * xbs;
   T += blockIdx.y * tbs;
+  const auto trs = make_rsrc_u(T, static_cast<unsigned>(NP) * 8u * static_cast<unsigned>(N));  // one signal's T
   const float2* rlo = tabs + kTabRotLo;
   // x holds xlen samples and the block starts at xoff (0 and N for a whole signal): frames at the block's
   // edges read the neighbouring samples, and only samples outside x read as zero.
@@ -211,12 +212,17 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       for (int r = 0; r < 4; ++r) xb[(kk * 4 + r) * kSeqStride + t + (t >> 4)] = col[r][8 * h + kk];
     }
     __syncthreads();
-    // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i.
+    // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i, stored at
+    // T[k][m1' / 16][m2][m1' % 16] = T[k][j / 4 + 4 i][m2][4 (j % 4) + r]: a per-butterfly lane offset plus
+    // i * 4 M2 * 16 elements, the latter a scalar offset of the buffer store.
     auto st = [&](int b, int m, float2 v) {
       const int k = c + S * (8 * h + (b >> 2));
-      const int m1p = (b & 3) + 4 * (m & 15) + 64 * (m >> 4);
-      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
-        T[((k * (kM1 / 16) + (m1p >> 4)) * M2 + m2) * 16 + (m1p & 15)] = cmul(v, rot[m1p]);
+      const int jj = m & 15, ii = m >> 4;
+      const int m1p = (b & 3) + 4 * jj + 64 * ii;
+      const unsigned voff = static_cast<unsigned>((((k * (kM1 / 16) + (jj >> 2)) * M2 + m2) * 16 + 4 * (jj & 3) +
+                                                   (b & 3)) * 8);
+      const unsigned soff = static_cast<unsigned>(ii) * (4u * 16u * 8u * static_cast<unsigned>(M2));
+      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);
@@ -320,7 +326,8 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
   const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (1024 * 16);
-  float2* dst = out + blockIdx.z * obs + static_cast<int64_t>(k) * N + mb * 16;
+  // S[k][q] of this workgroup's rows: q = 16 mb + row + 1024 (i' + 32 j'), through a buffer over strip k.
+  const auto ors = make_rsrc_u(out + blockIdx.z * obs + static_cast<int64_t>(k) * N, 8u * static_cast<unsigned>(N));
   const int rp = tid & 7, j = tid >> 3;
   float2 a[32], b[32];
 #pragma unroll
@@ -348,8 +355,9 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
     for (int jj = 0; jj < 32; ++jj) v[jj] = buf[ipl * kP2XStride + jj * 16 + row];
     dft32(v);
     const int ip = 16 * h + ipl;
+    const unsigned voff = static_cast<unsigned>(mb * 16 + row + kM1 * ip) * 8u;
 #pragma unroll
-    for (int jp = 0; jp < 32; ++jp) st1_nt(dst + static_cast<int64_t>(ip + 32 * jp) * kM1 + row, v[jp]);
+    for (int jp = 0; jp < 32; ++jp) store_c64<true>(ors, v[jp], voff, static_cast<unsigned>(jp) * (32u * kM1 * 8u));
   }
 }
 

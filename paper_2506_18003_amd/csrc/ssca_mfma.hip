@@ -332,6 +332,7 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
   xhi += blockIdx.y * pbs;
   xlo += blockIdx.y * pbs;
   T += blockIdx.y * tbs;
+  const auto trs = make_rsrc_u(T, static_cast<unsigned>(NP) * 8u * static_cast<unsigned>(N));  // one signal's T
   const float2* rlo = tabs + kTabRotLo;
   const float2* tw_g = tabs + kTabTw1024;
   const auto xr = make_rsrc(x, N * 8);
@@ -444,11 +445,16 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
       }
     }
     __syncthreads();
+    // Output m = j + 16 i of sequence b goes to T[k][j / 4 + 4 i][m2][4 (j % 4) + b % 4] (as in the FP32 Stage 1):
+    // a per-butterfly lane offset plus a scalar offset of i * 4 M2 * 16 elements.
     auto st = [&](int b, int m, float2 v) {
       const int k = chalf + S * (8 * h + (b >> 2));
-      const int m1p = (b & 3) + 4 * (m & 15) + 64 * (m >> 4);
-      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
-        T[((k * (kM1 / 16) + (m1p >> 4)) * M2 + m2) * 16 + (m1p & 15)] = cmul(v, rot[m1p]);
+      const int jj = m & 15, ii = m >> 4;
+      const int m1p = (b & 3) + 4 * jj + 64 * ii;
+      const unsigned voff = static_cast<unsigned>((((k * (kM1 / 16) + (jj >> 2)) * M2 + m2) * 16 + 4 * (jj & 3) +
+                                                   (b & 3)) * 8);
+      const unsigned soff = static_cast<unsigned>(ii) * (4u * 16u * 8u * static_cast<unsigned>(M2));
+      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);

@@ -194,6 +194,93 @@ class Selector:
         c.conf_min = self.conf_min
         return c
 
+    def write_model_file(self, path):
+        """Write this selector as a model file (scd_model_write; no device needed)."""
+        host = lambda a: np.ascontiguousarray(np.asarray(a.cpu() if hasattr(a, "cpu") else a, np.float32))
+        Model.write(path, self.Np, host(self.params), host(self.mu), host(self.sigma), self.theta, self.conf_min)
+
+
+class Model:
+    """A library-owned selector (scd_model in include/scd.h): the MLP parameters and feature statistics live in
+    device memory of the device current at creation; created from host arrays, loaded from or saved to a model
+    file, and freed through the C ABI. Usable wherever a Selector is (``ssca_learned``)."""
+
+    def __init__(self, handle, Np, theta, conf_min):
+        self._h = handle
+        self.Np = Np
+        self.theta = theta
+        self.conf_min = conf_min
+
+    @staticmethod
+    def _host(a, n):
+        a = np.ascontiguousarray(np.asarray(a, np.float32))
+        if a.size != n:
+            raise ValueError(f"expected {n} values, got {a.size}")
+        return a
+
+    @staticmethod
+    def create(Np, params, mu, sigma, theta, conf_min):
+        p = Model._host(params, param_count(Np))
+        m, s = Model._host(mu, 2 * Np), Model._host(sigma, 2 * Np)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().scd_model_create(Np, p.ctypes.data, m.ctypes.data, s.ctypes.data, float(theta),
+                                               float(conf_min), ctypes.byref(h)))
+        return Model(h, Np, float(theta), float(conf_min))
+
+    @staticmethod
+    def write(path, Np, params, mu, sigma, theta, conf_min):
+        p = Model._host(params, param_count(Np))
+        m, s = Model._host(mu, 2 * Np), Model._host(sigma, 2 * Np)
+        _lib.check(_lib.lib().scd_model_write(os.fsencode(path), Np, p.ctypes.data, m.ctypes.data, s.ctypes.data,
+                                              float(theta), float(conf_min)))
+
+    @staticmethod
+    def load(path):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().scd_model_load(os.fsencode(path), ctypes.byref(h)))
+        c = _lib.ScdSelector()
+        _lib.check(_lib.lib().scd_model_selector(h, ctypes.byref(c)))
+        return Model(h, c.Np, float(c.theta), float(c.conf_min))
+
+    def save(self, path):
+        _lib.check(_lib.lib().scd_model_save(self._h, os.fsencode(path)))
+
+    def read(self):
+        """(params, mu, sigma) as host float32 arrays."""
+        p = np.empty(param_count(self.Np), np.float32)
+        m = np.empty(2 * self.Np, np.float32)
+        s = np.empty(2 * self.Np, np.float32)
+        _lib.check(_lib.lib().scd_model_read(self._h, p.ctypes.data, m.ctypes.data, s.ctypes.data))
+        return p, m, s
+
+    def c_struct(self):
+        c = _lib.ScdSelector()
+        _lib.check(_lib.lib().scd_model_selector(self._h, ctypes.byref(c)))
+        return c
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.check(_lib.lib().scd_model_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def export_model_files(models_dir=None):
+    """Write models/selector_np*.scdm from the trained selectors' .npz/.json files (host only)."""
+    d = models_dir or os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+    out = []
+    for f in sorted(os.listdir(d)):
+        if f.startswith("selector_np") and f.endswith(".npz"):
+            path = os.path.join(d, f[:-4] + ".scdm")
+            Selector.load(os.path.join(d, f)).write_model_file(path)
+            out.append(path)
+    return out
+
 
 def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None, want_fallback=True):
     """SSCA of one signal restricted to the strips the selector picks: (out, mask [Np] uint8, fell_back).
@@ -241,3 +328,13 @@ class Trainer:
 
     def state(self):
         return dict(params=self.params, m=self.m, v=self.v, t=self.t)
+
+
+if __name__ == "__main__":
+    import sys
+
+    if sys.argv[1:] == ["--export"]:
+        for p in export_model_files():
+            print(p)
+    else:
+        print("usage: python -m paper_2506_18003_amd.selector --export")

@@ -189,3 +189,103 @@ def test_ssca_block_errors(L):
     o = _lib.ScdOpts()
     o.precision = _lib.PRECISIONS["split_bf16"]
     assert L.scd_ssca_block_ex(_fake(X), 8192, 4096, 4096, 64, _fake(W), _fake(O), ctypes.byref(o)) == _lib.SCD_ERR_UNSUPPORTED
+
+
+# ---- selector model files and lifecycle (host-side checks; no device call is reached) ---------------------
+MODELS = os.path.join(ROOT, "paper_2506_18003_amd", "models")
+
+
+def _fnv1a(b: bytes) -> int:
+    h = 2166136261
+    for c in b:
+        h = ((h ^ c) * 16777619) & 0xFFFFFFFF
+    return h
+
+
+def _npz_model(Np):
+    import json
+    import numpy as np
+
+    d = np.load(os.path.join(MODELS, f"selector_np{Np}.npz"))
+    m = json.load(open(os.path.join(MODELS, f"selector_np{Np}.json")))
+    return (np.ascontiguousarray(d["params"], np.float32), np.ascontiguousarray(d["mu"], np.float32),
+            np.ascontiguousarray(d["sigma"], np.float32), m["theta"], m["conf_min"])
+
+
+def _write(L, path, Np, p, mu, sg, theta, conf):
+    return L.scd_model_write(os.fsencode(str(path)), Np, p.ctypes.data, mu.ctypes.data, sg.ctypes.data, theta, conf)
+
+
+@pytest.mark.parametrize("Np", [64, 128, 256])
+def test_model_file_layout_and_committed_files(L, tmp_path, Np):
+    """scd_model_write lays the file out as the header documents (parsed here with struct, hash recomputed), and
+    the committed .scdm files are exactly what it writes from the trained selectors' arrays."""
+    import struct
+
+    import numpy as np
+
+    p, mu, sg, theta, conf = _npz_model(Np)
+    path = tmp_path / "m.scdm"
+    assert _write(L, path, Np, p, mu, sg, theta, conf) == 0
+    b = path.read_bytes()
+    assert b[:4] == b"SCDM"
+    version, np_, n, th, cf = struct.unpack("<IiiFf".replace("F", "f"), b[4:24])
+    assert (version, np_, n) == (1, Np, L.scd_mlp_param_count(Np))
+    assert th == np.float32(theta) and cf == np.float32(conf)
+    arr = np.frombuffer(b[24:-4], np.float32)
+    assert np.array_equal(arr, np.concatenate([p, mu, sg]))
+    assert struct.unpack("<I", b[-4:])[0] == _fnv1a(b[:-4])
+    assert (open(os.path.join(MODELS, f"selector_np{Np}.scdm"), "rb").read()) == b
+
+
+def test_model_load_rejects_bad_files(L, tmp_path):
+    p, mu, sg, theta, conf = _npz_model(64)
+    good = tmp_path / "good.scdm"
+    assert _write(L, good, 64, p, mu, sg, theta, conf) == 0
+    b = good.read_bytes()
+    h = ctypes.c_void_p(123)
+    cases = {
+        "missing": None,
+        "magic": b"SCDX" + b[4:],
+        "version": b[:4] + (2).to_bytes(4, "little") + b[8:],
+        "np": b[:8] + (48).to_bytes(4, "little") + b[12:],
+        "truncated": b[:-100],
+        "extra": b + b"\0",
+        "corrupt": b[:1000] + bytes([b[1000] ^ 1]) + b[1001:],
+        "short": b[:10],
+    }
+    for name, content in cases.items():
+        path = tmp_path / f"{name}.scdm"
+        if content is not None:
+            path.write_bytes(content)
+        assert L.scd_model_load(os.fsencode(str(path)), ctypes.byref(h)) == _lib.SCD_ERR_MODEL, name
+        assert not h.value, name
+        assert L.scd_last_error()
+    assert L.scd_model_load(None, ctypes.byref(h)) == _lib.SCD_ERR_NULL
+    assert L.scd_model_load(os.fsencode(str(good)), None) == _lib.SCD_ERR_NULL
+
+
+def test_model_create_and_write_reject_bad_values(L, tmp_path):
+    import numpy as np
+
+    p, mu, sg, theta, conf = _npz_model(64)
+    h = ctypes.c_void_p()
+    create = lambda Np, pp, mm, ss, t, c, out=ctypes.byref(h): L.scd_model_create(
+        Np, pp.ctypes.data if pp is not None else None, mm.ctypes.data, ss.ctypes.data, t, c, out)
+    assert create(64, p, mu, sg, theta, conf, None) == _lib.SCD_ERR_NULL
+    assert create(64, None, mu, sg, theta, conf) == _lib.SCD_ERR_NULL
+    assert create(48, p, mu, sg, theta, conf) == _lib.SCD_ERR_SIZE
+    assert create(64, p, mu, sg, 1.5, conf) == _lib.SCD_ERR_MODEL
+    assert create(64, p, mu, sg, theta, -0.1) == _lib.SCD_ERR_MODEL
+    bad_sigma = sg.copy()
+    bad_sigma[3] = 0.0
+    assert create(64, p, mu, bad_sigma, theta, conf) == _lib.SCD_ERR_MODEL
+    bad_p = p.copy()
+    bad_p[1000] = np.nan
+    assert create(64, bad_p, mu, sg, theta, conf) == _lib.SCD_ERR_MODEL
+    assert _write(L, tmp_path / "x.scdm", 64, bad_p, mu, sg, theta, conf) == _lib.SCD_ERR_MODEL
+    assert _write(L, tmp_path / "no_such_dir" / "x.scdm", 64, p, mu, sg, theta, conf) == _lib.SCD_ERR_MODEL
+    assert L.scd_model_write(None, 64, p.ctypes.data, mu.ctypes.data, sg.ctypes.data, theta, conf) == _lib.SCD_ERR_NULL
+    assert L.scd_model_destroy(None) == 0
+    assert L.scd_model_save(None, b"x") == _lib.SCD_ERR_NULL
+    assert L.scd_model_selector(None, None) == _lib.SCD_ERR_NULL

@@ -49,22 +49,26 @@ def test_stream_of_blocks(dev):
     assert offs == [0, 4096, 8192, 12288]
 
 
-def test_receiver_streams_host_blocks(dev):
-    """Blocks pushed from pinned host memory come back, in order, equal bit for bit to ssca_block of the whole
-    signal resident on the device (copy and estimate overlap on two streams)."""
-    N, Np, nb = 4096, 64, 5
-    x = sg.qpsk(nb * N, 0.1, 8, 4.0, sg.rng_for(113, 0)).astype(np.complex64)
+@pytest.mark.parametrize("nb,slots,outputs", [(9, 4, 2), (5, 3, 1), (2, 4, 3), (1, 4, 2)])
+def test_receiver_streams_host_blocks(dev, nb, slots, outputs):
+    """Blocks pushed from pinned host memory through the receiver's fixed ring of device slots (more blocks
+    than slots, so slots and output buffers are reused) come back in order, equal bit for bit to ssca_block of
+    the whole signal resident on the device (copy and estimate overlap on two streams)."""
+    N, Np = 4096, 64
+    x = sg.qpsk(nb * N, 0.1, 8, 4.0, sg.rng_for(113, nb + slots), ).astype(np.complex64)
     full = torch.from_numpy(x).to(dev)
-    rx = scd.SscaReceiver(N, Np, nb * N, dev)
+    rx = scd.SscaReceiver(N, Np, dev, slots=slots, outputs=outputs)
     got = []
     for b in range(nb):
         blk = torch.empty(N, dtype=torch.complex64, pin_memory=True)
         blk.copy_(torch.from_numpy(x[b * N:(b + 1) * N]))
         r = rx.push(blk)
         if r is not None:
-            got.append((r[0], r[1].clone()))
-    got.append(rx.finish())
+            got.append((r[0], r[1].clone()))  # the output buffer is reused `outputs` estimates later
+    off, S = rx.finish()
+    got.append((off, S.clone()))
     torch.cuda.synchronize()
     assert [o for o, _ in got] == [b * N for b in range(nb)]
     for off, S in got:
         assert torch.equal(S, scd.ssca_block(full, off, N, Np)), off
+    assert rx.ring.numel() == slots * (N + 2 * Np)  # fixed device memory, whatever the stream length
