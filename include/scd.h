@@ -327,6 +327,23 @@ typedef struct scd_ssca_item {
  * (nonzero strides), and those of scd_ssca_ex and scd_ssca_learned. */
 int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts);
 
+/*
+ * scd_ssca_noalloc - scd_ssca_ex (FP32, one signal) for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. It calls no hipMalloc, hipFree or
+ * other allocating routine. Its scratch (the FP64-generated tables, regenerated by every call, then the
+ * intermediate) is a file-scope device array that each GPU the library runs on holds until the process ends;
+ * scd_ssca_noalloc_limit() gives the intermediate's capacity (64 MiB), so 8 * Np * N must not exceed it
+ * (N == 1024 needs no intermediate). Every call on one GPU uses that GPU's one array: calls that overlap on one
+ * GPU (different streams, or threads without ordering) race and corrupt each other's results.
+ *   x, N, Np, win, out  as scd_ssca
+ *   opts                stream only: precision must be SCD_FP32, batch 0 or 1, no workspace (or opts NULL)
+ * Errors: SCD_ERR_NULL, SCD_ERR_SIZE (including 8 * Np * N above the limit), SCD_ERR_ALIAS, SCD_ERR_PTR,
+ * SCD_ERR_UNSUPPORTED (other precision, batch or a workspace), SCD_ERR_HIP. The result equals scd_ssca_ex's. */
+int scd_ssca_noalloc(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts);
+
+/* The intermediate capacity of scd_ssca_noalloc's scratch, in bytes. */
+size_t scd_ssca_noalloc_limit(void);
+
 /* Bytes of workspace scd_ssca_ex needs for `batch` signals (0 when N == 1024). Errors: SCD_ERR_NULL,
  * SCD_ERR_SIZE. */
 int scd_ssca_workspace_size(int64_t N, int Np, int batch, size_t* bytes);

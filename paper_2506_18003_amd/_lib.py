@@ -102,6 +102,8 @@ _SIGS = {
     "scd_ssca_learned": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ScdOpts)]),
     "scd_ssca_batch": (ctypes.c_int, [ctypes.POINTER(ScdSscaItem), ctypes.c_int, ctypes.POINTER(ScdOpts)]),
+    "scd_ssca_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
+    "scd_ssca_noalloc_limit": (ctypes.c_size_t, []),
     "scd_model_create": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "scd_model_destroy": (ctypes.c_int, [_P]),

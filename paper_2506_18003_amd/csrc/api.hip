@@ -851,3 +851,86 @@ void scd_shutdown(void) {
 }
 
 }  // extern "C"
+
+// ---- the no-allocation SSCA entry point -------------------------------------------------------------------
+// Its scratch is a file-scope device array: the FP64-generated tables, then one signal's intermediate. Every GPU
+// the library runs on holds its own copy until the process ends. Host code never passes the array's name to a
+// kernel: it takes the array's address on each device once (hipGetSymbolAddress, with that device current) and
+// uses that pointer.
+namespace {
+constexpr size_t kNoAllocTabBytes = 256 * ((sizeof(float2) * scd::kTabSize + 255) / 256);
+constexpr size_t kNoAllocInterBytes = size_t{64} << 20;
+constexpr size_t kNoAllocBytes = kNoAllocTabBytes + kNoAllocInterBytes;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// The device address of this device's scratch (library lock held).
+int noalloc_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SCD_ERR_UNSUPPORTED, "device %d is beyond the library's limit", dev);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return SCD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t scd_ssca_noalloc_limit(void) { return kNoAllocInterBytes; }
+
+int scd_ssca_noalloc(const float* x, int64_t N, int Np, const float* win, float* out, const scd_opts* opts) {
+  if (!x || !win || !out) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
+  if (!is_pow2(N) || N < 1024 || N > (1 << 20))
+    return fail(SCD_ERR_SIZE, "N = %lld must be a power of two in [2^10, 2^20]", static_cast<long long>(N));
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_noalloc takes one signal per call");
+  if (opts && opts->precision != SCD_FP32) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_noalloc runs in FP32 only");
+  if (opts && (opts->workspace || opts->workspace_bytes))
+    return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_noalloc uses its own scratch, not a workspace");
+  const int64_t grid = static_cast<int64_t>(Np) * N;
+  const size_t inter = N > 1024 ? 8u * static_cast<size_t>(grid) : 0;
+  if (inter > kNoAllocInterBytes)
+    return fail(SCD_ERR_SIZE, "Np * N * 8 = %zu bytes exceeds the %zu-byte scratch of scd_ssca_noalloc", inter,
+                kNoAllocInterBytes);
+  const size_t ob = 8u * static_cast<size_t>(grid);
+  if (overlaps(out, ob, x, 8u * static_cast<size_t>(N)) || overlaps(out, ob, win, 4u * Np))
+    return fail(SCD_ERR_ALIAS, "output overlaps an input");
+  const hipStream_t s = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc, dev;
+  if ((rc = check_device_range(x, 8u * static_cast<size_t>(N), "x"))) return rc;
+  if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
+  if ((rc = check_device_range(out, ob, "out"))) return rc;
+  if ((rc = current_device(&dev))) return rc;
+  unsigned char* base;
+  if ((rc = noalloc_scratch(dev, &base))) return rc;
+  // Tables are regenerated by every call (the scratch keeps whatever the last call on this device left).
+  float2* tabs = reinterpret_cast<float2*>(base);
+  float2* T = reinterpret_cast<float2*>(base + kNoAllocTabBytes);
+  hipError_t e = scd::launch_gen_roots(tabs + scd::kTabTw1024, 1024, 1024, s);
+  if (e == hipSuccess) e = scd::launch_gen_roots(tabs + scd::kTabRotLo, 1024, static_cast<int>(N), s);
+  if (e == hipSuccess) e = scd::launch_gen_roots(tabs + scd::kTabRoots, Np, Np, s);
+  const scd::SelArg sel = scd::selarg_all(Np);
+  const float2* xc = reinterpret_cast<const float2*>(x);
+  float2* oc = reinterpret_cast<float2*>(out);
+  const int n = static_cast<int>(N);
+  if (e == hipSuccess) {
+    if (inter == 0) {  // N == 1024: the Stage 1 output is the result
+      e = scd::launch_ssca_pass1_fp32(xc, n, Np, win, tabs, oc, 1, N, grid, sel, s);
+    } else {
+      e = scd::launch_ssca_pass1_fp32(xc, n, Np, win, tabs, T, 1, N, grid, sel, s);
+      if (e == hipSuccess) e = scd::launch_ssca_pass2(T, n, Np, tabs, oc, 1, grid, grid, sel, s);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "scd_ssca_noalloc launch");
+  return SCD_OK;
+}
+
+}  // extern "C"
