@@ -456,6 +456,54 @@ def main():
                                   "algorithmic_bytes": pbytes}
         del pout
 
+    # The paper's own FAM workload (Sec. III-A worked sizes): N = 2048 samples, Np = 256, L = 64, P = 32, on the
+    # paper's DSSS BPSK test signal (SNR 10 dB, processing gain 31, chip rate 0.25) with a 100 dB Chebyshev
+    # window. One estimate at a time and a batch of estimates, each as the complex grid (scd_fam) and as the
+    # paper's kept |S|^2 bins (scd_fam_power); ms per estimate and input samples per second.
+    fam_paper = None
+    if not args.no_fam:
+        from scipy.signal.windows import chebwin
+
+        from synth import signals as SG
+
+        pNp, pL, pP = 256, 64, 32
+        pN = pL * pP
+        nb = 256
+        xs = np.stack([SG.dsss_bpsk(pN, 10.0, SG.rng_for(8, i)) for i in range(nb)]).astype(np.complex64)
+        px = torch.from_numpy(xs).to(dev)
+        pw = torch.from_numpy(chebwin(pNp, at=100).astype(np.float32)).to(dev)
+        fam_paper = {"workload": f"FAM N={pN} Np={pNp} L={pL} P={pP} (DSSS BPSK, 10 dB, Chebyshev window)"}
+        for form, fn, shape, dt in (("complex", scd.fam, (pNp, pNp, pP), torch.complex64),
+                                    ("power", scd.fam_power, (pNp, pNp, pP // 2), torch.float32)):
+            o1 = torch.empty(*shape, dtype=dt, device=dev)
+            ob = torch.empty(nb, *shape, dtype=dt, device=dev)
+            for _ in range(args.warmup):
+                fn(px[0], pNp, pL, pP, win=pw, out=o1)
+                fn(px, pNp, pL, pP, win=pw, out=ob)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            reps = max(10, args.steps)
+            torch.cuda.synchronize()
+            e[0].record(stream)
+            for i in range(reps):
+                fn(px[i % nb], pNp, pL, pP, win=pw, out=o1)
+            e[1].record(stream)
+            fn(px, pNp, pL, pP, win=pw, out=ob)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            one = e[0].elapsed_time(e[1]) / reps
+            bat = e[1].elapsed_time(e[2])
+            outb = ob.numel() * ob.element_size() // nb
+            bytes_per = 8 * pN + 2 * 8 * pNp * pP + outb
+            fam_paper[form] = {
+                "ms_per_estimate": round(one, 5), "input_MS_per_s": round(pN / (one * 1e-3) / 1e6, 1),
+                "batch": nb, "batch_ms": round(bat, 5), "batch_ms_per_estimate": round(bat / nb, 6),
+                "batch_input_MS_per_s": round(nb * pN / (bat * 1e-3) / 1e6, 1),
+                "batch_hbm_GBs": round(nb * bytes_per / (bat * 1e-3) / 1e9, 1),
+                "batch_hbm_frac": round(nb * bytes_per / (bat * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del o1, ob
+        fam_paper["paper_context"] = "VCK5000 0.630 ms per estimate, 3.25 MS/s (Table II/III; other hardware)"
+        del px
+
     cpu = None
     errs = {}
     if not args.no_cpu_baseline:
@@ -501,6 +549,8 @@ def main():
     }
     if fam_line is not None:
         line["fam"] = fam_line
+    if fam_paper is not None:
+        line["fam_paper"] = fam_paper
     if learned_info is not None:
         li = learned_info
         line["forms"]["learned"] = {

@@ -304,6 +304,15 @@ int scd_select(const float* scores, int Np, int batch, float theta, unsigned cha
 int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
                      unsigned char* mask, int* fell_back, const scd_opts* opts);
 
+/* The selector half of scd_ssca_learned on one signal, without the SSCA: the features, then the same fused
+ * kernel chain (standardise, MLP, threshold at selector->theta, fallback to every strip below
+ * selector->conf_min). scores: device Np floats (the sigmoid outputs); mask: device Np bytes (1 = the strip
+ * scd_ssca_learned would compute); conf: device float, min_k max(s_k, 1 - s_k) (may be NULL); fell_back: device
+ * int, 1 when the fallback applies (may be NULL). Asynchronous on the stream of opts. Arguments, sizes and
+ * errors as scd_ssca_learned. */
+int scd_selector_run(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* scores,
+                     unsigned char* mask, float* conf, int* fell_back, const scd_opts* opts);
+
 /* One signal of scd_ssca_batch. */
 typedef struct scd_ssca_item {
   const float* x;               /* device, N complex values                                                */

@@ -101,6 +101,8 @@ _SIGS = {
     "scd_select": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_float, _P, _P, _P]),
     "scd_ssca_learned": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P,
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ScdOpts)]),
+    "scd_selector_run": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdSelector), _P, _P, _P,
+                                        _P, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_batch": (ctypes.c_int, [ctypes.POINTER(ScdSscaItem), ctypes.c_int, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_noalloc_limit": (ctypes.c_size_t, []),

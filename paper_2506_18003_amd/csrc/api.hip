@@ -752,21 +752,24 @@ int scd_select(const float* scores, int Np, int batch, float theta, unsigned cha
   return SCD_OK;
 }
 
-int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
-                     unsigned char* mask, int* fell_back, const scd_opts* opts) {
-  if (!x || !win || !selector || !out || !mask) return fail(SCD_ERR_NULL, "NULL argument");
+}  // extern "C"
+
+namespace {
+// The selector half of the learned form: features, then one kernel chain that standardises them, runs the MLP,
+// thresholds the scores, falls back below the confidence floor and writes the device-side selection. Leaves
+// the scores at *scores (device, Np floats), the confidence and fallback flag at *conf / *fell and the
+// ChanSel at *dsel, all in the library's selector scratch (checked arguments; takes the library lock itself).
+int learned_select(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector,
+                   unsigned char* mask, hipStream_t stream, float** scores, float** conf, int** fell,
+                   scd::ChanSel** dsel) {
+  if (!x || !win || !selector || !mask) return fail(SCD_ERR_NULL, "NULL argument");
   if (!selector->params || !selector->mu || !selector->sigma) return fail(SCD_ERR_MODEL, "selector has NULL arrays");
   if (reinterpret_cast<uintptr_t>(selector->params) % 16 != 0)
     return fail(SCD_ERR_MODEL, "selector params must be 16-byte aligned");
   if (selector->Np != Np) return fail(SCD_ERR_MODEL, "selector was trained for Np = %d, not %d", selector->Np, Np);
-  if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_learned takes one signal per call");
-  if (opts && opts->precision != SCD_FP32 && opts->precision != SCD_SPLIT_BF16)
-    return fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
   if (!is_pow2(N) || N < (1 << 14) || N > (1 << 20))
     return fail(SCD_ERR_SIZE, "the learned form needs N a power of two in [2^14, 2^20]");
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
-  hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
-  // Selector scratch: features, then (after the training-sized slots) confidence, fallback flag, selection.
   const scd::MlpLayout L = scd::mlp_layout(Np);
   int rc;
   float* f = nullptr;
@@ -778,24 +781,64 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
     if ((rc = check_device_range(selector->mu, 8u * Np, "selector mu"))) return rc;
     if ((rc = check_device_range(selector->sigma, 8u * Np, "selector sigma"))) return rc;
     if ((rc = check_device_range(mask, static_cast<size_t>(Np), "mask"))) return rc;
+    if ((rc = check_device_range(x, 8u * static_cast<size_t>(N), "x"))) return rc;
+    if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
     void* p;
     if ((rc = grow(&g_dev[dev].sel, &g_dev[dev].sel_bytes, 4u * kSelScratchFloats, &p))) return rc;
     f = static_cast<float*>(p);
-  }
-  float* conf = f + kSelScratchFloats - kSelStructFloats - 2;
-  int* dfell = reinterpret_cast<int*>(conf + 1);
-  scd::ChanSel* dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((rc = check_device_range(x, 8u * static_cast<size_t>(N), "x"))) return rc;
-    if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
     // Raw features: the first MLP layer centres the PSD part itself.
     if ((rc = features_impl(x, N, Np, win, f, 1, N, stream, false))) return rc;
   }
-  float* act = f + 2 * 256;  // activations and scores: 2 * 256 + Np floats
-  hipError_t e = scd::launch_select_infer(f, selector->mu, selector->sigma, selector->params, Np, selector->theta,
-                                          selector->conf_min, act, mask, conf, dfell, dsel, stream);
+  *conf = f + kSelScratchFloats - kSelStructFloats - 2;
+  *fell = reinterpret_cast<int*>(*conf + 1);
+  *dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
+  float* act = f + 2 * 256;  // h1, h2 (256 each), then the Np scores
+  *scores = act + 2 * 256;
+  const hipError_t e = scd::launch_select_infer(f, selector->mu, selector->sigma, selector->params, Np,
+                                                selector->theta, selector->conf_min, act, mask, *conf, *fell, *dsel,
+                                                stream);
   if (e != hipSuccess) return hip_fail(e, "selector");
+  return SCD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int scd_selector_run(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* scores,
+                     unsigned char* mask, float* conf, int* fell_back, const scd_opts* opts) {
+  if (!scores) return fail(SCD_ERR_NULL, "NULL argument");
+  if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_selector_run takes one signal per call");
+  hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((rc = check_device_range(scores, 4u * Np, "scores"))) return rc;
+    if (conf && (rc = check_device_range(conf, 4u, "conf"))) return rc;
+    if (fell_back && (rc = check_device_range(fell_back, 4u, "fell_back"))) return rc;
+  }
+  float *dsc, *dconf;
+  int* dfell;
+  scd::ChanSel* dsel;
+  if ((rc = learned_select(x, N, Np, win, selector, mask, stream, &dsc, &dconf, &dfell, &dsel))) return rc;
+  hipError_t e = hipMemcpyAsync(scores, dsc, 4u * Np, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && conf) e = hipMemcpyAsync(conf, dconf, 4u, hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && fell_back) e = hipMemcpyAsync(fell_back, dfell, 4u, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "selector result copy");
+  return SCD_OK;
+}
+
+int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector, float* out,
+                     unsigned char* mask, int* fell_back, const scd_opts* opts) {
+  if (!x || !win || !selector || !out || !mask) return fail(SCD_ERR_NULL, "NULL argument");
+  if (opts && opts->batch > 1) return fail(SCD_ERR_UNSUPPORTED, "scd_ssca_learned takes one signal per call");
+  if (opts && opts->precision != SCD_FP32 && opts->precision != SCD_SPLIT_BF16)
+    return fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
+  hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
+  int rc;
+  float *dsc, *dconf;
+  int* dfell;
+  scd::ChanSel* dsel;
+  if ((rc = learned_select(x, N, Np, win, selector, mask, stream, &dsc, &dconf, &dfell, &dsel))) return rc;
   // The grids cover every subset and strip; the kernels read the selection from dsel and skip the rest.
   const scd::SelArg sel{dsel, Np / 16, Np / 32, Np};
   scd_opts so{};
@@ -804,7 +847,7 @@ int scd_ssca_learned(const float* x, int64_t N, int Np, const float* win, const 
   so.stream = stream;
   if ((rc = ssca_common(SscaPart::kWhole, x, N, Np, win, out, &so, &sel))) return rc;
   if (fell_back) {
-    e = hipMemcpyAsync(fell_back, dfell, sizeof(int), hipMemcpyDeviceToHost, stream);
+    hipError_t e = hipMemcpyAsync(fell_back, dfell, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "fallback flag read-back");
   }

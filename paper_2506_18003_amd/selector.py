@@ -282,6 +282,28 @@ def export_model_files(models_dir=None):
     return out
 
 
+def run_selector(x, sel, win=None):
+    """The selector half of ssca_learned on one signal (scd_selector_run): (scores [Np] float32, mask [Np] uint8,
+    conf [1] float32, fell_back [1] int32), all device tensors, enqueued on the current stream."""
+    torch = _torch()
+    from . import _window, _check_x
+    _check_x(x)
+    N = x.shape[-1]
+    Np = sel.Np
+    w = _window(win, Np, x.device)
+    scores = torch.empty(Np, dtype=torch.float32, device=x.device)
+    mask = torch.empty(Np, dtype=torch.uint8, device=x.device)
+    conf = torch.empty(1, dtype=torch.float32, device=x.device)
+    fell = torch.empty(1, dtype=torch.int32, device=x.device)
+    o = _lib.ScdOpts()
+    o.stream = _stream(x)
+    cs = sel.c_struct()
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_selector_run(x.data_ptr(), N, Np, w.data_ptr(), ctypes.byref(cs), scores.data_ptr(),
+                                               mask.data_ptr(), conf.data_ptr(), fell.data_ptr(), ctypes.byref(o)))
+    return scores, mask, conf, fell
+
+
 def ssca_learned(x, sel: Selector, win=None, precision="fp32", out=None, want_fallback=True):
     """SSCA of one signal restricted to the strips the selector picks: (out, mask [Np] uint8, fell_back).
     With want_fallback=False the call stays asynchronous (no read-back) and fell_back is None."""

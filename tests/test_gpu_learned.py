@@ -68,27 +68,82 @@ def _params_dict(p, Np):
     return out
 
 
-@pytest.mark.parametrize("Np,B", [(16, 37), (64, 70)])
-def test_mlp_forward_backward_match_bf16_reference(dev, Np, B):
-    """Both sides round every GEMM operand to bf16; the remaining differences come from FP32 vs FP64
-    accumulation (an operand that lands within one bf16 ulp of a rounding boundary may round differently)."""
+TOL_GEMM = 1e-4  # |GPU - FP64| per element, relative to the sum of |terms| (the dot product's error scale)
+
+
+def _bf(a):
+    return LR.bf16_round(np.asarray(a, np.float64))
+
+
+def _check_gemm(got, A, B, bias=None, name=""):
+    """got == bf16(A) @ bf16(B) (+ bias) element by element, within TOL_GEMM of the absolute-sum scale: both sides
+    take the same bf16-rounded operands, so only the FP32 accumulation order differs."""
+    a, b = _bf(A), _bf(B)
+    ref = a @ b + (0.0 if bias is None else bias)
+    scale = np.abs(a) @ np.abs(b) + (0.0 if bias is None else np.abs(bias)) + 1e-30
+    err = np.abs(np.asarray(got, np.float64) - ref) / scale
+    assert err.max() <= TOL_GEMM, (name, float(err.max()))
+
+
+@pytest.mark.parametrize("Np,B", [(16, 37), (64, 70), (128, 33), (256, 20)])
+def test_mlp_forward_backward_match_bf16_reference_elementwise(dev, Np, B):
+    """Every layer of the forward and backward pass, element by element: each GPU GEMM against the FP64 product
+    of the same bf16-rounded operands (taken from the GPU's own previous layer), within 1e-4 of the dot
+    product's absolute-sum scale; ReLU, the sigmoid and the BCE gradient to FP32 rounding."""
     rng = np.random.default_rng(Np + B)
     p = SEL.init_params(Np, seed=3)
-    p[SEL.layout(Np)["b1"][0]:][:SEL.HIDDEN] = rng.standard_normal(SEL.HIDDEN) * 0.1
+    for name in ("b1", "b2", "b3"):
+        off, size = SEL.layout(Np)[name]
+        p[off:off + size] = rng.standard_normal(size) * 0.1
     X = rng.standard_normal((B, 2 * Np)).astype(np.float32)
     Y = (rng.random((B, Np)) > 0.6).astype(np.float32)
     pg, Xg, Yg = gpu(p, dev, torch.float32), gpu(X, dev, torch.float32), gpu(Y, dev, torch.float32)
     act, z, s = SEL.mlp_forward(pg, Xg, Np)
-    grads, dx = SEL.mlp_backward(pg, Xg, act, s, Yg, Np, want_dx=True)
+    grads = torch.empty_like(pg)
+    scratch = torch.empty(B * (Np + 2 * SEL.HIDDEN), dtype=torch.float32, device=dev)
+    dx = torch.empty_like(Xg)
+    from paper_2506_18003_amd import _lib
+    _lib.check(_lib.lib().scd_mlp_backward(Np, B, pg.data_ptr(), Xg.data_ptr(), act.data_ptr(), s.data_ptr(),
+                                           Yg.data_ptr(), grads.data_ptr(), scratch.data_ptr(), dx.data_ptr(),
+                                           torch.cuda.current_stream(dev).cuda_stream))
     P = _params_dict(p, Np)
+    a1, h1, a2, h2 = (t.cpu().numpy().astype(np.float64) for t in act)
+    z, s = z.cpu().numpy().astype(np.float64), s.cpu().numpy().astype(np.float64)
+    # forward
+    _check_gemm(a1, X, P["W1"].T, P["b1"], "a1")
+    assert np.array_equal(h1, np.maximum(a1, 0.0))
+    _check_gemm(a2, h1, P["W2"].T, P["b2"], "a2")
+    assert np.array_equal(h2, np.maximum(a2, 0.0))
+    _check_gemm(z, h2, P["W3"].T, P["b3"], "z")
+    assert np.abs(s - 1.0 / (1.0 + np.exp(-z))).max() <= 4e-7
+    # backward
+    sc = scratch.cpu().numpy().astype(np.float64)
+    dz = sc[:B * Np].reshape(B, Np)
+    d2 = sc[B * Np:B * Np + B * SEL.HIDDEN].reshape(B, SEL.HIDDEN)
+    d1 = sc[B * Np + B * SEL.HIDDEN:].reshape(B, SEL.HIDDEN)
+    assert np.abs(dz - (s - Y) / (B * Np)).max() <= 1e-6 / (B * Np)
+    g = _params_dict(grads.cpu().numpy(), Np)
+    _check_gemm(g["W3"], dz.T, h2, name="dW3")
+    assert np.abs(g["b3"] - dz.sum(axis=0)).max() <= TOL_GEMM * np.abs(dz).sum(axis=0).max()
+    assert np.array_equal(d2, d2 * (a2 > 0))  # the ReLU mask of layer 2
+    pre2 = _bf(dz) @ _bf(P["W3"])
+    scale2 = np.abs(_bf(dz)) @ np.abs(_bf(P["W3"])) + 1e-30
+    assert (np.abs(d2 - pre2 * (a2 > 0)) / scale2).max() <= TOL_GEMM
+    _check_gemm(g["W2"], d2.T, h1, name="dW2")
+    assert np.abs(g["b2"] - d2.sum(axis=0)).max() <= TOL_GEMM * np.abs(d2).sum(axis=0).max() + 1e-30
+    pre1 = _bf(d2) @ _bf(P["W2"])
+    scale1 = np.abs(_bf(d2)) @ np.abs(_bf(P["W2"])) + 1e-30
+    assert (np.abs(d1 - pre1 * (a1 > 0)) / scale1).max() <= TOL_GEMM
+    _check_gemm(g["W1"], d1.T, X, name="dW1")
+    assert np.abs(g["b1"] - d1.sum(axis=0)).max() <= TOL_GEMM * np.abs(d1).sum(axis=0).max() + 1e-30
+    _check_gemm(dx.cpu().numpy(), d1, P["W1"], name="dx")
+    # End to end against the FP64 reference's own chain: operands that land on either side of a bf16 rounding
+    # boundary add up to 8 * 2^-8 of the absolute-sum scale (the bound the CPU pin of the reference uses).
     cache = LR.mlp_forward(P, X.astype(np.float64), bf16=True)
-    assert np.abs(s.cpu().numpy() - cache["s"]).max() <= 5e-3
-    g = LR.mlp_backward(P, X.astype(np.float64), Y.astype(np.float64), cache, bf16=True)
-    gg = _params_dict(grads.cpu().numpy(), Np)
-    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        num = np.linalg.norm(gg[name] - g[name])
-        assert num <= 2e-2 * np.linalg.norm(g[name]) + 1e-9, name
-    assert np.linalg.norm(dx.cpu().numpy() - g["F"]) <= 2e-2 * np.linalg.norm(g["F"])
+    gr = LR.mlp_backward(P, X.astype(np.float64), Y.astype(np.float64), cache, bf16=True)
+    bound = 8 * 2.0 ** -8
+    scale_w3 = np.abs(_bf(cache["s"] - Y)).T @ np.abs(_bf(cache["h2"])) / (B * Np) + 1e-30
+    assert (np.abs(g["W3"] - gr["W3"]) / scale_w3).max() <= bound
 
 
 def test_adam_matches_reference(dev):
@@ -234,27 +289,76 @@ def test_trained_selector_recall_on_held_out_cfg4(dev):
 
 
 def test_combined_workload_split_bf16_learned(dev):
-    """The combined form on signals of the cfg-5 recipe (uneven lengths 2^14..2^20, Np = 64): split-BF16 +
-    learned selection + fallback. Every selected strip equals the full split-BF16 SSCA's, the recall over the
-    labels of the full FP32 SSCA is >= 0.99, and the split-BF16 strips stay within 1e-3 of the FP64 oracle."""
+    """The combined form on signals of the cfg-5 recipe (uneven lengths 2^14..2^20; Np = 64 for even indices,
+    128 for odd): split-BF16 + learned selection + fallback. Every selected strip equals the full split-BF16
+    SSCA's, the recall over the labels of the full FP32 SSCA is >= 0.99 for each Np, and the split-BF16 strips
+    stay within 1e-3 of the FP64 oracle."""
     from synth import workloads as W
-    sel = _model(64, dev)
-    tp = pos = 0
-    for i in range(0, 16, 2):  # the even indices of the workload use Np = 64
+    sels = {64: _model(64, dev), 128: _model(128, dev)}
+    tp = {64: 0, 128: 0}
+    pos = {64: 0, 128: 0}
+    for i in range(16):
         c = W.cfg5_signal(i)
+        Np = c["Np"]
+        assert Np == (64 if i % 2 == 0 else 128)
         x = torch.from_numpy(c["x"].astype(np.complex64)).to(dev)
-        out, mask, fb = SEL.ssca_learned(x, sel, precision="split_bf16")
-        full32 = scd.ssca(x, 64)
-        full16 = scd.ssca(x, 64, precision="split_bf16")
+        out, mask, fb = SEL.ssca_learned(x, sels[Np], precision="split_bf16")
+        full32 = scd.ssca(x, Np)
+        full16 = scd.ssca(x, Np, precision="split_bf16")
         m = mask.cpu().numpy().astype(bool)
         lab = SEL.strip_labels(full32)[0].cpu().numpy()[0] > 0.5
-        tp += (m & lab).sum()
-        pos += lab.sum()
+        tp[Np] += (m & lab).sum()
+        pos[Np] += lab.sum()
         k = torch.from_numpy(np.nonzero(m)[0]).to(dev)
         assert torch.equal(out[k], full16[k]), i
         if m.any():
             kk = int(np.nonzero(m)[0][0])
-            ref = O.ssca_strip(f64(c["x"]), 64, sg.hamming(64).astype(np.float32).astype(np.float64), kk)
+            ref = O.ssca_strip(f64(c["x"]), Np, sg.hamming(Np).astype(np.float32).astype(np.float64), kk)
             g = out[kk].cpu().numpy()
             assert np.abs(g - ref).max() <= 1e-3 * np.abs(ref).max(), i
-    assert tp / max(1, pos) >= 0.99
+    for Np in (64, 128):
+        assert tp[Np] / max(1, pos[Np]) >= 0.99, Np
+
+
+def _random_selector(Np, dev, seed):
+    """A selector with non-zero random weights, biases and feature statistics (not trained)."""
+    rng = np.random.default_rng(seed)
+    p = SEL.init_params(Np, seed=seed)
+    for name in ("b1", "b2", "b3"):
+        off, size = SEL.layout(Np)[name]
+        p[off:off + size] = rng.standard_normal(size) * 0.3
+    mu = rng.standard_normal(2 * Np).astype(np.float32)
+    sigma = rng.uniform(0.5, 2.0, 2 * Np).astype(np.float32)
+    return SEL.Selector(Np, p, mu, sigma, theta=0.5, conf_min=0.6).to(dev)
+
+
+@pytest.mark.parametrize("Np,which", [(64, "trained"), (128, "trained"), (256, "trained"), (64, "random"),
+                                      (128, "random")])
+def test_fused_selector_chain_matches_reference(dev, Np, which):
+    """The fused inference chain of the learned form (raw features -> PSD centring and standardisation inside the
+    first layer -> bf16 GEMVs -> sigmoid -> threshold -> fallback), run alone by scd_selector_run, against the
+    FP64 reference of the same chain on the GPU's own features: scores element by element within the bf16
+    bound; mask and fallback equal to thresholding those scores; and scd_ssca_learned's mask equal to it."""
+    from synth import workloads as W
+    sel = _model(Np, dev) if which == "trained" else _random_selector(Np, dev, 7 + Np)
+    P = _params_dict(sel.params.cpu().numpy(), Np)
+    mu, sigma = sel.mu.cpu().numpy().astype(np.float64), sel.sigma.cpu().numpy().astype(np.float64)
+    for i in range(4):
+        xs = W.selector_signal(i, "test", emin=15, emax=16)[1] if Np < 256 else W.cfg4_signal(i, 1 << 16, "test")[1]
+        x = gpu(xs, dev)
+        scores, mask, conf, fell = SEL.run_selector(x, sel)
+        feat = SEL.features(x, Np).cpu().numpy()[0].astype(np.float64)  # PSD part centred, as the chain centres it
+        f = (feat - mu) / sigma
+        cache = LR.mlp_forward(P, f[None, :], bf16=True)
+        # |dz| <= 8 * 2^-8 * (abs-sum scale of the last layer); the sigmoid's slope is at most 1/4
+        zscale = np.abs(_bf(cache["h2"])) @ np.abs(_bf(P["W3"])).T + np.abs(P["b3"])
+        got = scores.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - cache["s"][0]) <= 0.25 * 8 * 2.0 ** -8 * zscale[0] + 1e-6), (i, Np, which)
+        m = mask.cpu().numpy().astype(bool)
+        c = float(np.min(np.maximum(got, 1 - got)))
+        assert abs(float(conf.item()) - c) <= 1e-7
+        fb = bool(fell.item())
+        assert fb == (c < sel.conf_min)
+        assert np.array_equal(m, np.ones(Np, bool) if fb else got >= sel.theta)
+        _, m2, fb2 = SEL.ssca_learned(x, sel)
+        assert np.array_equal(m2.cpu().numpy().astype(bool), m) and fb2 == fb
