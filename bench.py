@@ -346,7 +346,7 @@ def main():
             rx.finish()
             torch.cuda.synchronize()
             sms = (time.perf_counter() - t0) * 1e3 / npush
-            ring_bytes = rx.ring.numel() * 8 + sum(o.numel() * 8 for o in rx.out)
+            ring_bytes = rx.ring_bytes + sum(o.numel() * 8 for o in rx.out)
             del rx
         dbuf = torch.empty(N, dtype=torch.complex64, device=dev)
         ce = [torch.cuda.Event(enable_timing=True) for _ in range(2)]

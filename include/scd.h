@@ -122,6 +122,35 @@ int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, in
                       const scd_opts* opts);
 
 /*
+ * Streaming receiver: SSCA estimates of a continuous stream of host blocks of N samples (the block form of
+ * scd_ssca_block_ex over consecutive blocks, each with its true neighbouring samples at its edges; zeros only
+ * before the first block and after the last), in fixed device memory: a library-owned ring of `slots` blocks with
+ * Np samples of halo at its two ends, and the caller's output buffers used in rotation. Each push copies one host
+ * block on the receiver's own copy stream (default priority) and enqueues the estimate of the previous block on
+ * the caller's stream, ordered by events, so the copy of one block overlaps the estimate of an earlier one.
+ *
+ * scd_receiver_create: N, Np as scd_ssca (N >= Np); win: device Np floats (caller-owned, read by every estimate);
+ *   slots in [3, 64] (4 lets a copy overlap the estimate two blocks back); outputs: n_outputs (1..64) device
+ *   buffers of Np*N complex values each, caller-owned; stream: hipStream_t of the estimates (NULL: null stream).
+ *   Allocates the ring (8 (slots N + 2 Np) bytes) on the current device and synchronises once.
+ * scd_receiver_push: host_block holds N complex values, in pinned memory for the copy to be asynchronous; it
+ *   must not be modified until its copy has completed (scd_receiver_wait_copy). On return *out_index is the
+ *   output buffer that will hold the previous block's estimate in stream order, and *offset that block's first
+ *   sample (-1 and unchanged for the first push). A buffer is overwritten n_outputs estimates later.
+ * scd_receiver_finish: enqueues the last block's estimate (its right edge reads zeros), waits for every copy.
+ * scd_receiver_wait_copy: waits until every pushed block's copy has completed.
+ * scd_receiver_destroy: waits for the receiver's work, frees it (NULL is a no-op).
+ * Errors: SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_NOMEM, SCD_ERR_HIP, and those of scd_ssca_block_ex.
+ */
+typedef struct scd_receiver scd_receiver;
+int scd_receiver_create(int64_t N, int Np, const float* win, int slots, float* const* outputs, int n_outputs,
+                        void* stream, scd_receiver** rx);
+int scd_receiver_push(scd_receiver* rx, const float* host_block, int* out_index, int64_t* offset);
+int scd_receiver_finish(scd_receiver* rx, int* out_index, int64_t* offset);
+int scd_receiver_wait_copy(scd_receiver* rx);
+int scd_receiver_destroy(scd_receiver* rx);
+
+/*
  * scd_ssca_cross_ex - SSCA estimate of the cross SCD of x and y (Eq. (2) with y != x, Sec. II-A): the demodulate
  * of y has the SSCA's one-sample window, so the channel-data product takes conj(y[n]) where scd_ssca takes
  * conj(x[n]):

@@ -122,103 +122,68 @@ def ssca_stream(x, N: int, Np: int, win=None):
 
 
 class SscaReceiver:
-    """Continuous streaming SSCA of blocks of N samples arriving from the host, in fixed device memory.
-
-    Block c is copied from a pinned complex64 CPU tensor [N] into slot c mod `slots` of a device ring on a copy
-    stream (default priority). A slot holds Np samples of halo on each side of its block: the copy of block c
-    also writes its first Np samples into the right halo of block c - 1's slot and its last Np samples into the
-    left halo of block c + 1's slot, so the edge frames of every block read the true neighbouring samples (zeros
-    only before the first block and after the last). Block c - 1 is estimated with scd_ssca_block_ex on the
-    current stream once block c's copy has landed (an event orders them), into one of `outputs` output buffers
-    used in rotation, so the copy of one block overlaps the estimate of an earlier one. The copy of block c
-    waits for the estimate of block c + 1 - slots, the last one reading the memory it overwrites; four slots let
-    a copy run while the estimate two blocks back is still computing.
-
-    push(block) returns (offset, S [Np, N]) for the block before it (None for the first); finish() returns the
-    last block's estimate. A returned S is a view of an output buffer that the estimate `outputs` blocks later
-    overwrites, in stream order: read or copy it before then. A pushed host block must not be modified until its
-    copy has completed: copied(c) gives the event that marks it, and finish() waits for every copy. The estimates
-    equal ssca_block of the whole signal resident on the device, bit for bit."""
+    """Continuous streaming SSCA of blocks of N samples arriving from the host (scd_receiver_* in
+    include/scd.h): fixed device memory, a ring of `slots` device blocks owned by the library and `outputs`
+    output tensors owned here and reused in rotation. push(block) copies one pinned complex64 CPU tensor [N] on
+    the receiver's copy stream and enqueues the estimate of the block before it on the current stream; it
+    returns (offset, S [Np, N]) for that block (None for the first). finish() returns the last block's estimate.
+    A returned S is overwritten `outputs` estimates later, in stream order: read or copy it before then. A pushed
+    host block must not be modified until wait_copy() (or finish()) has returned; this object keeps a reference
+    to the last `slots` blocks meanwhile. The estimates equal ssca_block of the whole signal resident on the
+    device, bit for bit."""
 
     def __init__(self, N: int, Np: int, device, win=None, slots: int = 4, outputs: int = 2):
         torch = _torch()
-        if slots < 3 or outputs < 1:
-            raise ValueError("a receiver needs at least 3 slots and 1 output buffer")
-        self.N, self.Np, self.device, self.win = N, Np, torch.device(device), win
-        self.H = Np                        # halo: frames reach Np/2 - 1 samples left and Np/2 samples right
-        self.S = N + 2 * self.H            # slot length
-        self.slots, self.nout = slots, outputs
-        cur = torch.cuda.current_stream(self.device)
+        self.N, self.Np, self.device = N, Np, torch.device(device)
+        self.win = _window(win, Np, self.device)
         with torch.cuda.device(self.device):
-            # Only halos that no block ever writes need zeros: the left halo of slot 0 (before the first block);
-            # finish() clears the right halo of the last block's slot itself.
-            self.ring = torch.zeros(slots * self.S, dtype=torch.complex64, device=self.device)
             self.out = [torch.empty(Np, N, dtype=torch.complex64, device=self.device) for _ in range(outputs)]
-            self.copy_stream = torch.cuda.Stream(self.device)
-        self.copy_stream.wait_stream(cur)  # the zero fill above runs on the current stream
-        self.count = 0
-        self._copied = {}      # block -> event recorded after its copies
-        self._estimated = {}   # block -> event recorded after its estimate
-        self._hold = {}        # block -> host tensor, kept alive until its copy has completed
+            ptrs = (ctypes.c_void_p * outputs)(*[o.data_ptr() for o in self.out])
+            self._h = ctypes.c_void_p()
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _lib.check(_lib.lib().scd_receiver_create(N, Np, self.win.data_ptr(), slots, ptrs, outputs, stream,
+                                                      ctypes.byref(self._h)))
+        self.slots = slots
+        self.ring_bytes = 8 * (slots * N + 2 * Np)
+        self._hold = []
 
-    def _slot(self, c):
-        return (c % self.slots) * self.S
-
-    def copied(self, c):
-        """Event recorded on the copy stream after block c's copies (None once it has been released)."""
-        return self._copied.get(c)
-
-    def _estimate(self, b, last=False):
-        torch = _torch()
-        cur = torch.cuda.current_stream(self.device)
-        cur.wait_event(self._copied[b + (0 if last else 1)])
-        base = self._slot(b)
-        if last:  # nothing follows the last block: its right halo reads zeros
-            self.ring[base + self.H + self.N: base + self.S].zero_()
-        S = self.out[b % self.nout]
-        ssca_block(self.ring[base: base + self.S], self.H, self.N, self.Np, win=self.win, out=S)
-        ev = torch.cuda.Event()
-        ev.record(cur)
-        self._estimated[b] = ev
-        self._estimated.pop(b - self.slots, None)
-        return b * self.N, S
+    def _result(self, idx, off):
+        return None if idx.value < 0 else (off.value, self.out[idx.value])
 
     def push(self, block):
         """Enqueue one host block; returns the estimate of the block before it, or None for the first."""
         torch = _torch()
-        N, H = self.N, self.H
-        if block.shape != (N,) or block.dtype != torch.complex64 or block.device.type != "cpu":
-            raise ValueError(f"a block is a complex64 CPU tensor of {N} samples")
-        c = self.count
-        # Release host blocks whose copies have completed (bounded host references).
-        for old in [k for k in self._hold if k < c - 1]:
-            if self._copied[old].query():
-                del self._hold[old]
-                del self._copied[old]
-        with torch.cuda.stream(self.copy_stream):
-            prior = self._estimated.get(c + 1 - self.slots)
-            if prior is not None:
-                self.copy_stream.wait_event(prior)
-            base = self._slot(c)
-            self.ring[base + H: base + H + N].copy_(block, non_blocking=True)
-            if c >= 1:
-                pb = self._slot(c - 1)
-                self.ring[pb + H + N: pb + self.S].copy_(block[:H], non_blocking=True)
-            nb = self._slot(c + 1)
-            self.ring[nb: nb + H].copy_(block[N - H:], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.copy_stream)
-        self._copied[c] = ev
-        self._hold[c] = block
-        self.count += 1
-        return self._estimate(c - 1) if c >= 1 else None
+        if block.shape != (self.N,) or block.dtype != torch.complex64 or block.device.type != "cpu":
+            raise ValueError(f"a block is a complex64 CPU tensor of {self.N} samples")
+        if not block.is_contiguous():
+            raise ValueError("a block must be contiguous")
+        idx, off = ctypes.c_int(-1), ctypes.c_int64(0)
+        _lib.check(_lib.lib().scd_receiver_push(self._h, block.data_ptr(), ctypes.byref(idx), ctypes.byref(off)))
+        self._hold.append(block)
+        if len(self._hold) > self.slots:
+            self._hold.pop(0)
+        return self._result(idx, off)
+
+    def wait_copy(self):
+        _lib.check(_lib.lib().scd_receiver_wait_copy(self._h))
 
     def finish(self):
         """Estimate the last block (zeros after it) and wait for every copy."""
-        out = self._estimate(self.count - 1, last=True) if self.count else None
-        self.copy_stream.synchronize()
+        idx, off = ctypes.c_int(-1), ctypes.c_int64(0)
+        _lib.check(_lib.lib().scd_receiver_finish(self._h, ctypes.byref(idx), ctypes.byref(off)))
         self._hold.clear()
-        return out
+        return self._result(idx, off)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().scd_receiver_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ssca_cross(x, y, Np: int, win=None, conjugate=False, out=None, workspace=None):

@@ -106,6 +106,12 @@ _SIGS = {
     "scd_ssca_batch": (ctypes.c_int, [ctypes.POINTER(ScdSscaItem), ctypes.c_int, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_noalloc_limit": (ctypes.c_size_t, []),
+    "scd_receiver_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, _P, ctypes.c_int, ctypes.POINTER(_P),
+                                           ctypes.c_int, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    "scd_receiver_push": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
+    "scd_receiver_finish": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]),
+    "scd_receiver_wait_copy": (ctypes.c_int, [_P]),
+    "scd_receiver_destroy": (ctypes.c_int, [_P]),
     "scd_model_create": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_float, ctypes.c_float,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "scd_model_destroy": (ctypes.c_int, [_P]),

@@ -192,6 +192,12 @@ size_t span_bytes(int batch, int64_t stride, int64_t len) {
 
 }  // namespace
 
+namespace scd {
+// Error reporting for the library's other host files (the calling thread's scd_last_error message).
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+int set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+}  // namespace scd
+
 extern "C" {
 
 int scd_version(void) { return (1 << 16) | 0; }

@@ -41,6 +41,10 @@ inline SelArg selarg_all(int Np) { return SelArg{nullptr, Np / 16, Np / 32, Np};
 
 hipError_t launch_gen_roots(float2* dst, int count, int M, hipStream_t stream);
 
+// Set the calling thread's scd_last_error message and return `code` (SCD_ERR_HIP for set_hip_error).
+int set_error(int code, const char* msg);
+int set_hip_error(hipError_t e, const char* what);
+
 // SSCA Stage 1 (channelizer + CDP + M1-point DFT + rotation) of `batch` signals. x: [batch][N] at stride xbs;
 // win: device float[Np]; T: [batch] blocked intermediates [Np][M1/16][M2][16] at stride tbs (float2 elements).
 // With N == 1024 the intermediate layout equals the output layout [Np][N]. ymode 1 (cross) or 2 (conjugate)

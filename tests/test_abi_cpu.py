@@ -289,3 +289,23 @@ def test_model_create_and_write_reject_bad_values(L, tmp_path):
     assert L.scd_model_destroy(None) == 0
     assert L.scd_model_save(None, b"x") == _lib.SCD_ERR_NULL
     assert L.scd_model_selector(None, None) == _lib.SCD_ERR_NULL
+
+
+def test_receiver_rejects_bad_arguments(L):
+    h = ctypes.c_void_p(1)
+    outs = (ctypes.c_void_p * 2)(_fake(O), _fake(O + 0x10000000))
+    create = lambda N, Np, win, slots, o, n, out=ctypes.byref(h): L.scd_receiver_create(N, Np, win, slots, o, n, None, out)
+    assert create(1 << 16, 64, _fake(W), 4, outs, 2, None) == _lib.SCD_ERR_NULL
+    assert create(1 << 16, 64, None, 4, outs, 2) == _lib.SCD_ERR_NULL and not h.value
+    assert create(1 << 16, 64, _fake(W), 4, None, 2) == _lib.SCD_ERR_NULL
+    assert create(1000, 64, _fake(W), 4, outs, 2) == _lib.SCD_ERR_SIZE
+    assert create(1 << 21, 64, _fake(W), 4, outs, 2) == _lib.SCD_ERR_SIZE
+    assert create(1 << 16, 48, _fake(W), 4, outs, 2) == _lib.SCD_ERR_SIZE
+    assert create(1 << 16, 64, _fake(W), 2, outs, 2) == _lib.SCD_ERR_SIZE
+    assert create(1 << 16, 64, _fake(W), 4, outs, 0) == _lib.SCD_ERR_SIZE
+    nul = (ctypes.c_void_p * 2)(_fake(O), None)
+    assert create(1 << 16, 64, _fake(W), 4, nul, 2) == _lib.SCD_ERR_NULL
+    assert L.scd_receiver_push(None, _fake(X), None, None) == _lib.SCD_ERR_NULL
+    assert L.scd_receiver_finish(None, None, None) == _lib.SCD_ERR_NULL
+    assert L.scd_receiver_wait_copy(None) == _lib.SCD_ERR_NULL
+    assert L.scd_receiver_destroy(None) == 0

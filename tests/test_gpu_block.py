@@ -71,4 +71,4 @@ def test_receiver_streams_host_blocks(dev, nb, slots, outputs):
     assert [o for o, _ in got] == [b * N for b in range(nb)]
     for off, S in got:
         assert torch.equal(S, scd.ssca_block(full, off, N, Np)), off
-    assert rx.ring.numel() == slots * (N + 2 * Np)  # fixed device memory, whatever the stream length
+    assert rx.ring_bytes == 8 * (slots * N + 2 * Np)  # fixed device memory, whatever the stream length
