@@ -282,7 +282,21 @@ struct NoStore {};
 // omega_{NS R}^{i (j mod NS)}, takes an R-point DFT and writes output i to (j/NS)*NS*R + (j mod NS) + i*NS.
 // BFAST selects the enumeration of butterflies over threads: sequence index fastest (true) or j fastest.
 // All threads read their inputs before the barrier and write after it, so the stage runs in place.
-template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, class LoadF, class StoreF>
+// Ordering between the phases of a stage. WAVE false: a workgroup barrier. WAVE true: only the issuing wave's
+// own LDS accesses need ordering (LDS executes one wave's instructions in order), so a compiler fence and a
+// wave barrier suffice.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, bool WAVE = false, class LoadF, class StoreF>
 __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   static_assert(TWN >= L, "the twiddle table must hold at least L roots");
   constexpr int R = StageRadix<L, NS>::value;
@@ -313,7 +327,8 @@ __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, in
       dft<R>(v[p]);
     }
   }
-  if constexpr (!LOAD_EXT) __syncthreads();
+  // In place: every read of the stage before any write. With WAVE and an external store nothing is written.
+  if constexpr (!LOAD_EXT && !(WAVE && STORE_EXT)) stage_sync<WAVE>();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
     const int bf = tid + p * NT;
@@ -329,15 +344,15 @@ __device__ __forceinline__ void stockham_stage(float2* buf, const float2* tw, in
       }
     }
   }
-  if constexpr (!STORE_EXT) __syncthreads();
+  if constexpr (!STORE_EXT) stage_sync<WAVE>();
 }
 
-template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, class LoadF, class StoreF>
+template <int L, int NB, int NT, int NS, bool BFAST, class Lay, int TWN, bool WAVE = false, class LoadF, class StoreF>
 __device__ __forceinline__ void stockham_from(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   if constexpr (NS < L) {
-    stockham_stage<L, NB, NT, NS, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
+    stockham_stage<L, NB, NT, NS, BFAST, Lay, TWN, WAVE>(buf, tw, tid, ld, st);
     constexpr int R = StageRadix<L, NS>::value;
-    stockham_from<L, NB, NT, NS * R, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
+    stockham_from<L, NB, NT, NS * R, BFAST, Lay, TWN, WAVE>(buf, tw, tid, ld, st);
   }
 }
 
@@ -394,10 +409,23 @@ __device__ __forceinline__ void stockham_rest(float2* buf, const float2* tw, int
 // Requires a barrier before the call if the data were just written to LDS by other threads. On return the
 // outputs are either in LDS (followed by a barrier) or were handed to `st(b, m, value)`.
 // `tw` holds omega_TWN^e for e < TWN (TWN >= L, a power of two).
-template <int L, int NB, int NT, bool BFAST, class Lay, int TWN = 1024, class LoadF, class StoreF>
+//
+// WAVE true drops the workgroup barriers between and inside the stages. That is valid when every stage has the
+// same butterfly count per sequence, L / R <= 64 dividing 64, with sequences enumerated j fastest (BFAST
+// false) over a multiple of 64 threads: then the threads of a sequence lie in one wave in every stage, and
+// only that wave touches the sequence's LDS. The caller still needs a workgroup barrier before the call if
+// other waves wrote the inputs, and after it before the buffer is reused.
+template <int L, int NS>
+constexpr bool uniform_radix() {
+  if constexpr (NS * StageRadix<L, NS>::value >= L) return true;
+  else return StageRadix<L, NS>::value == StageRadix<L, 1>::value && uniform_radix<L, NS * StageRadix<L, NS>::value>();
+}
+template <int L, int NB, int NT, bool BFAST, class Lay, int TWN = 1024, bool WAVE = false, class LoadF, class StoreF>
 __device__ __forceinline__ void lds_fft(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   static_assert(L >= 2 && L <= 1024 && (L & (L - 1)) == 0, "length must be a power of two in [2, 1024]");
-  stockham_from<L, NB, NT, 1, BFAST, Lay, TWN>(buf, tw, tid, ld, st);
+  static_assert(!WAVE || (!BFAST && NT % 64 == 0 && uniform_radix<L, 1>() && 64 % (L / StageRadix<L, 1>::value) == 0),
+                "wave-local stages need one wave per sequence in every stage");
+  stockham_from<L, NB, NT, 1, BFAST, Lay, TWN, WAVE>(buf, tw, tid, ld, st);
 }
 
 }  // namespace scd

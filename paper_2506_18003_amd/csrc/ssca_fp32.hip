@@ -224,8 +224,11 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       const unsigned soff = static_cast<unsigned>(ii) * (4u * 16u * 8u * static_cast<unsigned>(M2));
       if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
+    // Each 256-point sequence's butterflies stay in one wave in both radix-16 stages, so past the barrier above
+    // the stages need no workgroup barrier. That pays in a paired workgroup (one per CU: a barrier stalls the
+    // whole CU), not measurably in the single-subset one.
     NoLoad ld;
-    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);
+    lds_fft<kSeq, kHalfSeqs, kP1Threads, false, LdsLayout<kSeqStride, 1, 4>, kSeq, PAIR>(xb, tw, t, ld, st);
   }
 }
 

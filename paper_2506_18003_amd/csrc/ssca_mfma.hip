@@ -457,7 +457,8 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
       if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
     NoLoad ld;
-    lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>, kSeq>(xb, tw, t, ld, st);
+    // Wave-local radix-16 stages, as in the paired FP32 Stage 1.
+    lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>, kSeq, true>(xb, tw, t, ld, st);
   }
 }
 
