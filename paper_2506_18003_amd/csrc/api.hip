@@ -650,7 +650,7 @@ int scd_mlp_param_count(int Np) {
 }
 
 namespace {
-// Segment SSCAs and the feature reduction of `batch` signals (checked arguments, library lock held).
+// Segment periodograms and the feature reduction of `batch` signals (checked arguments, library lock held).
 int features_impl(const float* x, int64_t N, int Np, const float* win, float* feat, int batch, int64_t xs,
                   hipStream_t stream, bool centre) {
   int rc, dev;
@@ -658,19 +658,19 @@ int features_impl(const float* x, int64_t N, int Np, const float* win, float* fe
   DevState& st = g_dev[dev];
   float2* tabs;
   if ((rc = get_tables(st, 1024, Np, stream, &tabs))) return rc;
-  const size_t segb = 8u * 16u * static_cast<size_t>(Np) * 1024u;
+  // Segment periodograms of up to kFeatChunk signals per launch.
+  constexpr int kFeatChunk = 8;
+  const int chunk = batch < kFeatChunk ? batch : kFeatChunk;
+  const size_t pb = 4u * 16u * static_cast<size_t>(Np) * 1024u * static_cast<size_t>(chunk);
   void* lrn;
-  if ((rc = get_lrn(st, segb, &lrn))) return rc;
-  float2* seg = static_cast<float2*>(lrn);
-  const scd::SelArg sel = scd::selarg_all(Np);
+  if ((rc = get_lrn(st, pb, &lrn))) return rc;
+  float* P = static_cast<float*>(lrn);
   const float2* xc = reinterpret_cast<const float2*>(x);
   hipError_t e = hipSuccess;
-  for (int b = 0; b < batch && e == hipSuccess; ++b) {
-    // 16 segments of 1024 samples, each an SSCA of its own (zero outside the segment).
-    e = scd::launch_ssca_pass1_fp32(xc + b * xs, 1024, Np, win, tabs, seg, 16, N / 16,
-                                    static_cast<int64_t>(Np) * 1024, sel, stream);
-    if (e == hipSuccess)
-      e = scd::launch_acp_features(seg, Np, 1, feat + static_cast<size_t>(b) * 2 * Np, stream, centre);
+  for (int b = 0; b < batch && e == hipSuccess; b += chunk) {
+    const int n = batch - b < chunk ? batch - b : chunk;
+    e = scd::launch_features(xc + b * xs, xs, N, Np, n, win, tabs, P, feat + static_cast<size_t>(b) * 2 * Np, stream,
+                             centre);
   }
   if (e != hipSuccess) return hip_fail(e, "feature launch");
   return SCD_OK;

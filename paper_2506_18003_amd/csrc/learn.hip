@@ -1,7 +1,8 @@
 // Kernels of the learned strip selector: features, labels, the MLP (bf16 MFMA GEMMs with FP32 accumulation)
 // with its backward pass and Adam, and the strip selection.
 //
-// Features of a signal (2 Np floats): from the SSCA S_b of B_F = 16 segments of N_C = 1024 samples,
+// Features of a signal (2 Np floats): from the SSCA S_b of B_F = 16 segments of N_C = 1024 samples (each zero
+// outside itself; Eq. (6)-(7) with N = N_C, so M1 = 1024 and M2 = 1),
 //   A_k[q]  = sum_b |S_b[k][q]|^2 (averaged cyclic periodogram of strip k),
 //   PSD_k   = 0.5 log(A_k[q0(k)] + 1e-30) centred over k, q0(k) = (-k_c N_C / Np) mod N_C (alpha = 0 bin),
 //   ACP_k   = log(max / mean of A_k over the bins farther than 4 (circularly) from q0(k)).
@@ -51,35 +52,155 @@ __device__ float block_max(float v, float* red) {
   return r;
 }
 
-// One workgroup per (strip k, signal): seg is [sig][B_F][Np][N_C] complex; feat [sig][2 Np] gets the raw
-// (uncentred) PSD_k and ACP_k.
-__global__ __launch_bounds__(256) void acp_features_kernel(const float2* __restrict__ seg, int Np,
-                                                           float* __restrict__ feat) {
-  __shared__ float red[256];
-  const int k = blockIdx.x, sig = blockIdx.y, tid = threadIdx.x;
-  const float2* base = seg + (static_cast<int64_t>(sig) * kBF * Np + k) * kNC;
-  const int q0 = (-signed_idx(k, Np) * (kNC / Np)) & (kNC - 1);
-  float sum = 0.f, mx = 0.f, a0 = 0.f;
-  int cnt = 0;
-  for (int q = tid; q < kNC; q += 256) {
-    float a = 0.f;
-    for (int b = 0; b < kBF; ++b) {
-      const float2 v = base[static_cast<int64_t>(b) * Np * kNC + q];
-      a = fmaf(v.x, v.x, fmaf(v.y, v.y, a));
-    }
-    if (q == q0) a0 = a;
-    const int d = abs(signed_idx((q - q0) & (kNC - 1), kNC));
-    if (d > 4) {
-      sum += a;
-      mx = fmaxf(mx, a);
-      ++cnt;
+constexpr int kSegThreads = 512;
+constexpr int kSegStride = kNC + kNC / 16;  // one float2 of padding per 16 elements
+
+// Periodograms P_b[k][q] = |S_b[k][q]|^2 of the B_F feature segments. One workgroup per (channel parity h,
+// subset c, segment b, signal): the 8 channels k = c + S (2 kk + h), kk < 8, S = Np / 16. Thread t owns the
+// adjacent frames m1 = 2t and 2t + 1 (frame n = m1 centred, samples outside the segment zero). Per frame:
+//   - the complex-windowed fold of the frame to 16 residues, A[j0] = sum_j1 hc[j0 + 16 j1] x[n - d + j0 + 16 j1],
+//     hc[j] = w[j] omega_Np^{(c j) mod Np}. The two frames' windows overlap, so each pair of samples read
+//     from LDS (and each pair of hc values) serves both frames' folds;
+//   - the parity-h half of its 16-point DFT: one decimation-in-frequency step,
+//     e[j0] = (A[j0] + (-1)^h A[j0 + 8]) omega_16^{h j0}, then an 8-point DFT (output kk is channel index 2 kk + h);
+//   - the down-conversion factor omega_Np^{(k n) mod Np} and conj(x[n]) (Eq. (6); M2 = 1, so n = m1).
+// Then the 1024-point DFT over m1 of the 8 channels in LDS, whose last stage writes |S_b[k][q]|^2.
+// P is [sig][B_F][Np][N_C]; the signals are xs complex apart and segment b starts at b N / B_F.
+template <int NP>
+__global__ __launch_bounds__(kSegThreads) void seg_periodogram_kernel(const float2* __restrict__ x, int64_t xs,
+                                                                     int64_t N, const float* __restrict__ win,
+                                                                     const float2* __restrict__ tabs,
+                                                                     float* __restrict__ P) {
+  constexpr int S = NP / 16;
+  constexpr int D = NP / 2 - 1;
+  constexpr int XL = kNC + NP - 1;  // samples the frames touch: n - D + j for n < N_C, j < NP
+  __shared__ float2 buf[8 * kSegStride];
+  __shared__ float2 tw[kNC];  // omega_1024^e
+  __shared__ __align__(16) float2 xl[XL + 1];  // xl[i] = segment sample i - D (zero outside the segment)
+  __shared__ __align__(16) float2 hc[NP];
+  __shared__ float2 rt[NP];   // omega_Np^e
+  const int h = blockIdx.x & 1, c = blockIdx.x >> 1, b = blockIdx.y, sig = blockIdx.z;
+  const int tid = threadIdx.x;
+  const float2* seg = x + sig * xs + static_cast<int64_t>(b) * (N / kBF);
+  for (int i = tid; i < XL + 1; i += kSegThreads) {
+    const int n = i - D;
+    xl[i] = (n >= 0 && n < kNC) ? seg[n] : make_float2(0.f, 0.f);
+  }
+  for (int i = tid; i < kNC; i += kSegThreads) tw[i] = tabs[kTabTw1024 + i];
+  for (int j = tid; j < NP; j += kSegThreads) {
+    rt[j] = tabs[kTabRoots + j];
+    hc[j] = cscale(tabs[kTabRoots + ((c * j) & (NP - 1))], win[j]);
+  }
+  __syncthreads();
+  // Fold of frames 2t (a0) and 2t + 1 (a1). xw[j] is tap j of frame 2t and tap j - 1 of frame 2t + 1; each
+  // residue sums its taps in increasing order.
+  float2 a0[16], a1[16];
+#pragma unroll
+  for (int j0 = 0; j0 < 16; ++j0) {
+    a0[j0] = make_float2(0.f, 0.f);
+    a1[j0] = make_float2(0.f, 0.f);
+  }
+  const float2* xw = xl + 2 * tid;
+  float2 hprev = make_float2(0.f, 0.f);  // hc[j - 1]
+#pragma unroll 1
+  for (int j1 = 0; j1 < NP / 16; ++j1) {
+#pragma unroll
+    for (int j0 = 0; j0 < 16; j0 += 2) {
+      const int j = 16 * j1 + j0;
+      const float4 xv = *reinterpret_cast<const float4*>(xw + j);  // 16-byte aligned: 2 tid + j is even
+      const float4 hv = *reinterpret_cast<const float4*>(hc + j);
+      const float2 x0 = make_float2(xv.x, xv.y), x1 = make_float2(xv.z, xv.w);
+      const float2 h0 = make_float2(hv.x, hv.y), h1 = make_float2(hv.z, hv.w);
+      a0[j0] = cfma(a0[j0], h0, x0);
+      a0[j0 + 1] = cfma(a0[j0 + 1], h1, x1);
+      if (j > 0) a1[(j0 + 15) & 15] = cfma(a1[(j0 + 15) & 15], hprev, x0);
+      a1[j0] = cfma(a1[j0], h0, x1);
+      hprev = h1;
     }
   }
-  const float tot = block_sum(sum, red);
-  const float n = block_sum(static_cast<float>(cnt), red);
-  const float m = block_max(mx, red);
-  const float a0s = block_sum(a0, red);
+  a1[15] = cfma(a1[15], hprev, xw[NP]);  // tap Np - 1 of frame 2t + 1
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const int m1 = 2 * tid + f;
+    float2* a = f ? a1 : a0;
+    float2 e[8];
+    if (h == 0) {
+#pragma unroll
+      for (int j0 = 0; j0 < 8; ++j0) e[j0] = cadd(a[j0], a[j0 + 8]);
+    } else {
+#pragma unroll
+      for (int j0 = 0; j0 < 8; ++j0) e[j0] = cmul(csub(a[j0], a[j0 + 8]), tw[64 * j0]);
+    }
+    dft8(e);
+    const float2 xn = xl[m1 + D];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = c + S * (2 * kk + h);
+      buf[kk * kSegStride + m1 + (m1 >> 4)] = cmul(e[kk], cmulc(rt[(k * m1) & (NP - 1)], xn));
+    }
+  }
+  __syncthreads();
+  float* Pb = P + (static_cast<int64_t>(sig) * kBF + b) * NP * kNC;
+  auto st = [&](int bq, int q, float2 v) {
+    const int k = c + S * (2 * bq + h);
+    Pb[k * kNC + q] = fmaf(v.x, v.x, v.y * v.y);
+  };
+  NoLoad ld;
+  lds_fft<kNC, 8, kSegThreads, false, LdsLayout<kSegStride, 1, 4>, kNC>(buf, tw, tid, ld, st);
+}
+
+// One workgroup per (strip k, signal): A_k[q] = sum_b P_b[k][q] in segment order; feat [sig][2 Np] gets the
+// raw (uncentred) PSD_k and ACP_k. Every load of a thread is issued before the sums; the four reductions
+// share one pass across the wave and one through LDS.
+__global__ __launch_bounds__(256) void acp_features_kernel(const float* __restrict__ P, int Np,
+                                                           float* __restrict__ feat) {
+  constexpr int QT = kNC / 256;  // bins per thread: q = QT tid + r
+  static_assert(QT == 4, "one float4 of bins per thread and segment");
+  __shared__ float red[4][4];
+  const int k = blockIdx.x, sig = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const float* base = P + (static_cast<int64_t>(sig) * kBF * Np + k) * kNC + QT * tid;
+  const int q0 = (-signed_idx(k, Np) * (kNC / Np)) & (kNC - 1);
+  float4 pv[kBF];
+#pragma unroll
+  for (int b = 0; b < kBF; ++b) pv[b] = *reinterpret_cast<const float4*>(base + static_cast<int64_t>(b) * Np * kNC);
+  float a[QT] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int b = 0; b < kBF; ++b) {
+    a[0] += pv[b].x;
+    a[1] += pv[b].y;
+    a[2] += pv[b].z;
+    a[3] += pv[b].w;
+  }
+  float sum = 0.f, mx = 0.f, a0 = 0.f, cnt = 0.f;
+#pragma unroll
+  for (int r = 0; r < QT; ++r) {
+    const int q = QT * tid + r;
+    if (q == q0) a0 = a[r];
+    if (abs(signed_idx((q - q0) & (kNC - 1), kNC)) > 4) {
+      sum += a[r];
+      mx = fmaxf(mx, a[r]);
+      cnt += 1.f;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    sum += __shfl_xor(sum, m, 64);
+    cnt += __shfl_xor(cnt, m, 64);
+    a0 += __shfl_xor(a0, m, 64);
+    mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+  }
+  if (lane == 0) {
+    red[w][0] = sum;
+    red[w][1] = cnt;
+    red[w][2] = a0;
+    red[w][3] = mx;
+  }
+  __syncthreads();
   if (tid == 0) {
+    const float tot = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    const float n = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    const float a0s = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
+    const float m = fmaxf(fmaxf(red[0][3], red[1][3]), fmaxf(red[2][3], red[3][3]));
     feat[sig * 2 * Np + k] = 0.5f * logf(a0s + 1e-30f);
     feat[sig * 2 * Np + Np + k] = logf(m / (tot / n));
   }
@@ -241,72 +362,156 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// One dense layer of selector inference, spread over the GPU: wave w of block b computes row o = 4 b + w,
-// out[o] = act(sum_i bf16(W[o][i]) in[i] + b[o]) with FP32 accumulation. Its lanes read 64 consecutive weights
-// per load (whole 256-byte runs, all NIN/64 loads in flight) and the row sum is reduced across the wave.
-// FIRST: in = bf16(standardised features) computed here from the raw features (PSD not yet centred: each wave
-// subtracts the mean PSD itself), mu and sigma; otherwise in is the previous layer's output (already
-// bf16-valued). ACT: 0 = ReLU then bf16 rounding (the next layer's operand), 1 = sigmoid.
-template <int NIN, bool FIRST, int ACT>
-__global__ __launch_bounds__(256) void mlp_infer_layer_kernel(const float* __restrict__ W, const float* __restrict__ bias,
-                                                              const float* __restrict__ in,
-                                                              const float* __restrict__ mu,
-                                                              const float* __restrict__ sigma, int nout,
-                                                              float* __restrict__ out) {
-  constexpr int C = NIN >= 64 ? NIN / 64 : 1;
-  const int lane = threadIdx.x & 63;
-  const int o = 4 * blockIdx.x + (threadIdx.x >> 6);
-  if (o >= nout) return;
-  const bool live = NIN >= 64 || lane < NIN;
-  float wv[C], xv[C];
-#pragma unroll
-  for (int cc = 0; cc < C; ++cc) wv[cc] = live ? W[static_cast<int64_t>(o) * NIN + 64 * cc + lane] : 0.f;
-  float mean = 0.f;
-  if constexpr (FIRST) {
-    constexpr int NPF = NIN / 2;  // PSD entries
-    float ps = 0.f;
-    for (int i = lane; i < NPF; i += 64) ps += in[i];
-    mean = wave_sum(ps) / static_cast<float>(NPF);
-  }
-#pragma unroll
-  for (int cc = 0; cc < C; ++cc) {
-    const int i = 64 * cc + lane;
-    float v = 0.f;
-    if (live) v = FIRST ? bf16r((in[i] - (i < NIN / 2 ? mean : 0.f) - mu[i]) / sigma[i]) : in[i];
-    xv[cc] = v;
-  }
-  float acc = 0.f;
-#pragma unroll
-  for (int cc = 0; cc < C; ++cc) acc = fmaf(bf16r(wv[cc]), xv[cc], acc);
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    acc += bias[o];
-    out[o] = (ACT == 0) ? bf16r(fmaxf(acc, 0.f)) : 1.f / (1.f + expf(-acc));
-  }
+// v from another lane by a DPP pattern; lanes of rows outside ROW_MASK get 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+}
+// Sum over the wave, held by lane 63: pairs and quads (quad permutations), 8 and 16 lanes (half-row and row
+// mirrors), then rows 0 + 1 and 2 + 3 (row broadcast of lane 15), then all four (row broadcast of lane 31).
+// DPP moves are plain VALU operations, with none of the LDS latency of a cross-lane shuffle.
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+  v += dpp_f<0xb1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_f<0x4e>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_f<0x141>(v);       // row_half_mirror
+  v += dpp_f<0x140>(v);       // row_mirror
+  v += dpp_f<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
 }
 
-// Strip selection of one signal from its scores: mask, confidence min_k max(s_k, 1 - s_k), fallback to every
-// strip below conf_min, and the channel selection the SSCA kernels read (strip list in increasing k from wave
-// ballots and per-wave counts, subset and pair lists from the kept strips).
+// Selector inference of one signal in one workgroup of 1024 threads (16 waves), which removes the launches
+// between the layers:
+//   - standardise the raw features: the PSD part is centred over k first, then bf16-round each input;
+//   - three dense layers: wave w computes a block of rows, the lanes reading 64 consecutive weights per load
+//     (whole 256-byte runs); a row is out[o] = act(sum_i bf16(W[o][i]) in[i] + b[o]) with FP32 accumulation in
+//     the order of the lanes' chunks, then a DPP reduction across the wave. The next layer's weights are loaded
+//     before the current layer's arithmetic, so each layer waits for memory about once;
+//   - the selection: mask, confidence min_k max(s_k, 1 - s_k), fallback to every strip below conf_min, and the
+//     channel selection the SSCA kernels read (strip list in increasing k from wave ballots and per-wave
+//     counts, subset and pair lists from the kept strips).
+// The activations (h1, h2 and the Np scores) are also written to act.
+constexpr int kInferThreads = 1024;
+constexpr int kInferWaves = kInferThreads / 64;
+
+// One dense layer: wave w owns the NOUT / 16 consecutive rows from w NOUT / 16. Its weights are loaded in
+// batches of RB rows (every load of a batch in flight at once, at most 64 registers), one batch when they fit.
+// ACT: 0 = ReLU then bf16 rounding (the next layer's operand), 1 = sigmoid. `bias`, `in` and `out` are in LDS.
+template <int NIN, int NOUT>
+struct Dense {
+  static constexpr int C = NIN >= 64 ? NIN / 64 : 1;  // weight loads per row and lane
+  static constexpr int R = NOUT / kInferWaves;        // rows per wave
+  static constexpr int RB = R * C <= 64 ? R : 64 / C; // rows per batch of loads
+  static_assert(NOUT % kInferWaves == 0 && R % RB == 0, "rows must split evenly over the waves");
+  __device__ __forceinline__ static void load(const float* __restrict__ W, int r0, int w, int lane, float (&wv)[RB][C]) {
+    const bool live = NIN >= 64 || lane < NIN;
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc)
+        wv[u][cc] = live ? W[static_cast<int64_t>(w * R + r0 + u) * NIN + 64 * cc + lane] : 0.f;
+  }
+  template <int ACT>
+  __device__ __forceinline__ static void rows(const float (&wv)[RB][C], const float* bias, const float* in,
+                                              float* out, int r0, int w, int lane) {
+    const bool live = NIN >= 64 || lane < NIN;
+    float xv[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) xv[cc] = live ? in[64 * cc + lane] : 0.f;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      float acc = 0.f;
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) acc = fmaf(bf16r(wv[u][cc]), xv[cc], acc);
+      acc = wave_sum_lane63(acc);
+      const int o = w * R + r0 + u;
+      if (lane == 63) {
+        acc += bias[o];
+        out[o] = (ACT == 0) ? bf16r(fmaxf(acc, 0.f)) : 1.f / (1.f + expf(-acc));
+      }
+    }
+  }
+  // The whole layer; `first` holds the weights of the first batch if they were loaded ahead.
+  template <int ACT>
+  __device__ __forceinline__ static void run(const float* __restrict__ W, const float* bias, const float* in,
+                                             float* out, int w, int lane, float (&first)[RB][C]) {
+    rows<ACT>(first, bias, in, out, 0, w, lane);
+    for (int r0 = RB; r0 < R; r0 += RB) {
+      float wv[RB][C];
+      load(W, r0, w, lane, wv);
+      rows<ACT>(wv, bias, in, out, r0, w, lane);
+    }
+  }
+};
+
 template <int NP>
-__global__ __launch_bounds__(256) void select_finish_kernel(const float* __restrict__ sc, float theta, float conf_min,
-                                                            unsigned char* __restrict__ mask,
-                                                            float* __restrict__ conf_out, int* __restrict__ fell,
-                                                            ChanSel* __restrict__ sel) {
-  __shared__ float red[4];
-  __shared__ int wcnt[4];
-  __shared__ unsigned long long wbits[4];
+__global__ __launch_bounds__(kInferThreads) void select_infer_kernel(
+    const float* __restrict__ feat, const float* __restrict__ mu, const float* __restrict__ sigma,
+    const float* __restrict__ params, float theta, float conf_min, float* __restrict__ act,
+    unsigned char* __restrict__ mask, float* __restrict__ conf_out, int* __restrict__ fell,
+    ChanSel* __restrict__ sel) {
+  constexpr int NIN = 2 * NP;
+  constexpr int S = NP / 16;
+  __shared__ float x0[NIN];
+  __shared__ float bs[2 * kHidden + NP];  // the three layers' biases
+  __shared__ float h1[kHidden];
+  __shared__ float h2[kHidden];
+  __shared__ float sc[NP];
+  __shared__ float red[kInferWaves];
+  __shared__ int wcnt[kInferWaves];
+  __shared__ unsigned long long wbits[kInferWaves];
   __shared__ unsigned char keep[NP];
   __shared__ unsigned char used[16];
-  constexpr int S = NP / 16;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const MlpLayout L = mlp_layout(NP);
+  using D1 = Dense<NIN, kHidden>;
+  using D2 = Dense<kHidden, kHidden>;
+  using D3 = Dense<kHidden, NP>;
+  float w1[D1::RB][D1::C];  // the first layer's weights load while the features are standardised
+  D1::load(params + L.W1, 0, w, lane, w1);
+  if (w == 0) {
+    float ps = 0.f;
+    for (int i = lane; i < NP; i += 64) ps += feat[i];
+    ps = wave_sum(ps);
+    if (lane == 0) red[0] = ps / static_cast<float>(NP);
+  }
+  __syncthreads();
+  const float mean = red[0];
+  for (int i = tid; i < NIN; i += kInferThreads) x0[i] = bf16r((feat[i] - (i < NP ? mean : 0.f) - mu[i]) / sigma[i]);
+  for (int i = tid; i < 2 * kHidden + NP; i += kInferThreads)
+    bs[i] = i < kHidden ? params[L.b1 + i] : i < 2 * kHidden ? params[L.b2 + i - kHidden] : params[L.b3 + i - 2 * kHidden];
+  __syncthreads();
+  // The next layer's first batch is issued before the current layer's arithmetic (in flight during it) when
+  // both batches fit in 96 registers; otherwise after it.
+  constexpr bool kPre2 = D1::RB * D1::C + D2::RB * D2::C <= 96;
+  constexpr bool kPre3 = D2::RB * D2::C + D3::RB * D3::C <= 96;
+  float w2[D2::RB][D2::C];
+  if constexpr (kPre2) D2::load(params + L.W2, 0, w, lane, w2);
+  D1::template run<0>(params + L.W1, bs, x0, h1, w, lane, w1);
+  if constexpr (!kPre2) D2::load(params + L.W2, 0, w, lane, w2);
+  __syncthreads();
+  float w3[D3::RB][D3::C];
+  if constexpr (kPre3) D3::load(params + L.W3, 0, w, lane, w3);
+  D2::template run<0>(params + L.W2, bs + kHidden, h1, h2, w, lane, w2);
+  if constexpr (!kPre3) D3::load(params + L.W3, 0, w, lane, w3);
+  __syncthreads();
+  D3::template run<1>(params + L.W3, bs + 2 * kHidden, h2, sc, w, lane, w3);
+  __syncthreads();
+  for (int i = tid; i < kHidden; i += kInferThreads) {
+    act[i] = h1[i];
+    act[kHidden + i] = h2[i];
+  }
   const float s = tid < NP ? sc[tid] : 0.5f;
+  if (tid < NP) act[2 * kHidden + tid] = s;
   float c = tid < NP ? fmaxf(s, 1.f - s) : 1.f;
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) c = fminf(c, __shfl_xor(c, m, 64));
+  __syncthreads();  // every wave has read red[0] (the PSD mean) above
   if (lane == 0) red[w] = c;
   __syncthreads();
-  const float conf = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+  float conf = red[0];
+#pragma unroll
+  for (int i = 1; i < kInferWaves; ++i) conf = fminf(conf, red[i]);
   const bool fb = conf < conf_min;
   const bool kp = tid < NP && (fb || s >= theta);
   if (tid < NP) {
@@ -330,12 +535,13 @@ __global__ __launch_bounds__(256) void select_finish_kernel(const float* __restr
   }
   __syncthreads();
   if (tid == 0) {
-    int nsub = 0, npair = 0;
+    int nsub = 0, npair = 0, nch = 0;
     for (int i = 0; i < S; ++i)
       if (used[i]) sel->sub[nsub++] = static_cast<unsigned char>(i);
     for (int i = 0; i < S / 2; ++i)
       if (used[i] || used[i + S / 2]) sel->pair[npair++] = static_cast<unsigned char>(i);
-    sel->nch = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    for (int i = 0; i < kInferWaves; ++i) nch += wcnt[i];
+    sel->nch = nch;
     sel->nsub = nsub;
     sel->npair = npair;
     *conf_out = conf;
@@ -345,19 +551,20 @@ __global__ __launch_bounds__(256) void select_finish_kernel(const float* __restr
 
 template <int NP>
 hipError_t select_infer(const float* feat, const float* mu, const float* sigma, const float* params, float theta,
-                        float conf_min, float* h, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
+                        float conf_min, float* act, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
                         hipStream_t s) {
-  const MlpLayout L = mlp_layout(NP);
-  float* h1 = h;
-  float* h2 = h + kHidden;
-  float* sc = h + 2 * kHidden;
-  hipLaunchKernelGGL((mlp_infer_layer_kernel<2 * NP, true, 0>), dim3(kHidden / 4), dim3(256), 0, s, params + L.W1,
-                     params + L.b1, feat, mu, sigma, kHidden, h1);
-  hipLaunchKernelGGL((mlp_infer_layer_kernel<kHidden, false, 0>), dim3(kHidden / 4), dim3(256), 0, s, params + L.W2,
-                     params + L.b2, h1, mu, sigma, kHidden, h2);
-  hipLaunchKernelGGL((mlp_infer_layer_kernel<kHidden, false, 1>), dim3(NP / 4), dim3(256), 0, s, params + L.W3,
-                     params + L.b3, h2, mu, sigma, NP, sc);
-  hipLaunchKernelGGL(select_finish_kernel<NP>, dim3(1), dim3(256), 0, s, sc, theta, conf_min, mask, conf, fell, sel);
+  hipLaunchKernelGGL(select_infer_kernel<NP>, dim3(1), dim3(kInferThreads), 0, s, feat, mu, sigma, params, theta,
+                     conf_min, act, mask, conf, fell, sel);
+  return hipGetLastError();
+}
+
+template <int NP>
+hipError_t seg_features(const float2* x, int64_t xs, int64_t N, int nsig, const float* win, const float2* tabs,
+                        float* P, float* feat, hipStream_t s, bool centre) {
+  hipLaunchKernelGGL(seg_periodogram_kernel<NP>, dim3(2 * (NP / 16), kBF, nsig), dim3(kSegThreads), 0, s, x, xs, N,
+                     win, tabs, P);
+  hipLaunchKernelGGL(acp_features_kernel, dim3(NP, nsig), dim3(256), 0, s, P, NP, feat);
+  if (centre) hipLaunchKernelGGL(centre_psd_kernel, dim3(nsig), dim3(256), 0, s, feat, NP);
   return hipGetLastError();
 }
 
@@ -373,10 +580,16 @@ hipError_t gemm(const float* A, int lda, const float* B, int ldb, float* C, floa
 
 }  // namespace
 
-hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t s, bool centre) {
-  hipLaunchKernelGGL(acp_features_kernel, dim3(Np, nsig), dim3(256), 0, s, seg, Np, feat);
-  if (centre) hipLaunchKernelGGL(centre_psd_kernel, dim3(nsig), dim3(256), 0, s, feat, Np);
-  return hipGetLastError();
+hipError_t launch_features(const float2* x, int64_t xs, int64_t N, int Np, int nsig, const float* win,
+                           const float2* tabs, float* P, float* feat, hipStream_t s, bool centre) {
+  switch (Np) {
+    case 16: return seg_features<16>(x, xs, N, nsig, win, tabs, P, feat, s, centre);
+    case 32: return seg_features<32>(x, xs, N, nsig, win, tabs, P, feat, s, centre);
+    case 64: return seg_features<64>(x, xs, N, nsig, win, tabs, P, feat, s, centre);
+    case 128: return seg_features<128>(x, xs, N, nsig, win, tabs, P, feat, s, centre);
+    case 256: return seg_features<256>(x, xs, N, nsig, win, tabs, P, feat, s, centre);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_labels(const float2* S, int64_t N, int Np, int nsig, float* labels, float* ratio, hipStream_t s) {

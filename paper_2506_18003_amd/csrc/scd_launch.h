@@ -94,9 +94,11 @@ __host__ __device__ inline MlpLayout mlp_layout(int Np) {
   L.total = L.b3 + Np;
   return L;
 }
-// seg: [nsig][16][Np][1024] segment SSCAs -> feat [nsig][2 Np] (PSD, centred over k if `centre`; ACP).
-hipError_t launch_acp_features(const float2* seg, int Np, int nsig, float* feat, hipStream_t stream,
-                               bool centre = true);
+// Selector features of nsig signals of N samples, xs complex apart: the segment periodograms go to P
+// ([nsig][16][Np][1024] floats of device scratch), then feat [nsig][2 Np] (PSD, centred over k if `centre`;
+// ACP). tabs: the tables of N = 1024 and this Np.
+hipError_t launch_features(const float2* x, int64_t xs, int64_t N, int Np, int nsig, const float* win,
+                           const float2* tabs, float* P, float* feat, hipStream_t stream, bool centre = true);
 // S: [nsig][Np][N] -> labels [nsig][Np] (0/1), ratio [nsig][Np] (may be null).
 hipError_t launch_labels(const float2* S, int64_t N, int Np, int nsig, float* labels, float* ratio,
                          hipStream_t stream);

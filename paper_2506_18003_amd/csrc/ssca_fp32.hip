@@ -42,7 +42,9 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 
 // Stage 1. Blocks run m2 fastest (see block_to_m2_unit for how that spreads x over the XCDs' L2 caches). With
 // a selection in device memory the grid covers every subset and the workgroups past the selected count exit
-// at once, so the host never needs to know the selection. A workgroup computes one channel subset (PAIR
+// at once, so the host never needs to know the selection. A selected subset writes all its strips to the
+// intermediate (Stage 2 reads and writes only the selected ones): a per-strip test on every store cost more
+// than the stores it saved. A workgroup computes one channel subset (PAIR
 // false: strips k = c mod Np/16) or a subset pair (PAIR true, Np >= 32: subsets c and c + Np/32) for one m2,
 // with 256 threads per subset; thread t of a subset owns frames m1 = t + 256 f (f < 4).
 //
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       const unsigned voff = static_cast<unsigned>((((k * (kM1 / 16) + (jj >> 2)) * M2 + m2) * 16 + 4 * (jj & 3) +
                                                    (b & 3)) * 8);
       const unsigned soff = static_cast<unsigned>(ii) * (4u * 16u * 8u * static_cast<unsigned>(M2));
-      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
+      store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
     // Each 256-point sequence's butterflies stay in one wave in both radix-16 stages, so past the barrier above
     // the stages need no workgroup barrier. That pays in a paired workgroup (one per CU: a barrier stalls the

@@ -261,8 +261,7 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
       float2 base = rot_factor(rlo, tw, m2 * rj, hishift);
       if constexpr (PHASE_BY_M2) base = cmul(base, rt[(k * m2) & (NP - 1)]);
       const int i = m >> 4;
-      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u))
-        st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
+      st1_nt(T + ((k * (kM1 / 16) + (rj >> 4)) * M2 + m2) * 16 + (rj & 15) + i * (64 * M2), cmul(v, cmul(base, stp[i])));
     };
     NoLoad ld;
     lds_fft<kSeq, kHalfSeqs, kThreads, false, LdsLayout<kSeqStride, 1, 4>>(buf, tw, tid, ld, st);
@@ -454,7 +453,7 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
       const unsigned voff = static_cast<unsigned>((((k * (kM1 / 16) + (jj >> 2)) * M2 + m2) * 16 + 4 * (jj & 3) +
                                                    (b & 3)) * 8);
       const unsigned soff = static_cast<unsigned>(ii) * (4u * 16u * 8u * static_cast<unsigned>(M2));
-      if (!SEL || ((sel->keep[k >> 5] >> (k & 31)) & 1u)) store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
+      store_c64<false>(trs, cmul(v, rot[m1p]), voff, soff);
     };
     NoLoad ld;
     // Wave-local radix-16 stages, as in the paired FP32 Stage 1.
