@@ -245,6 +245,12 @@ def main():
         # modulation and noise, SNR in [-10, 15] dB) at N = 2^20: what the selection buys when not every strip
         # carries a cyclic feature.
         mix_full, mix_learned, mix_strips, mix_tp, mix_pos, mix_fb = [], [], 0, 0, 0, 0
+        # The selector without its network: a threshold on the raw ACP feature, calibrated on the selector's
+        # validation split for the same strip recall (tau, stored with the model's training metrics).
+        with open(os.path.join(ROOT, "paper_2506_18003_amd", "models", f"selector_np{Np}.json")) as fh:
+            meta = json.load(fh)["meta"]
+        tau = meta["test_acp_threshold"]["tau"]
+        acp_strips, acp_tp = 0, 0
         for i in range(args.mix_signals):
             xm = torch.from_numpy(W.selector_signal(i, "test", emin=20, emax=20)[1].astype(np.complex64)).to(dev)
             for _ in range(2):
@@ -270,12 +276,24 @@ def main():
             mix_tp += int((mm & lab).sum())
             mix_pos += int(lab.sum())
             mix_fb += int(bool(fbm))
+            ma = SEL.features(xm, Np)[0, Np:].cpu().numpy() >= tau
+            acp_strips += int(ma.sum())
+            acp_tp += int((ma & lab).sum())
         if args.mix_signals:
             learned_info["mix"] = dict(
                 signals=args.mix_signals, full_ms=float(np.mean(mix_full)), learned_ms=float(np.mean(mix_learned)),
                 speedup_vs_fp32=float(np.mean(mix_full) / np.mean(mix_learned)),
                 strip_fraction=mix_strips / (args.mix_signals * Np), recall=mix_tp / max(1, mix_pos),
-                active_fraction=mix_pos / (args.mix_signals * Np), fallbacks=mix_fb)
+                active_fraction=mix_pos / (args.mix_signals * Np), fallbacks=mix_fb,
+                acp_threshold_strip_fraction=acp_strips / (args.mix_signals * Np),
+                acp_threshold_recall=acp_tp / max(1, mix_pos))
+        # The same comparison on the selector's own 2000-signal test split (from its training run).
+        learned_info["vs_acp_threshold"] = {
+            "split": f"test split of the selector recipe ({meta['recipe']['test']} signals, N = 2^U{{14..20}})",
+            "learned": meta["test_learned"], "learned_no_fallback": meta["test_learned_no_fallback"],
+            "acp_threshold": meta["test_acp_threshold"],
+            "network_strip_saving_vs_acp": round(meta["test_acp_threshold"]["work_fraction"]
+                                                 - meta["test_learned_no_fallback"]["work_fraction"], 5)}
     for form in forms:
         for _ in range(args.warmup):
             scd.ssca_stage1(x, Np, inter, win=win, precision=form)
@@ -298,6 +316,33 @@ def main():
         results[form] = dict(ms_per_step=ms, pass1_ms=float(np.mean(p1)), pass2_ms=float(np.mean(p2)),
                              step_ms_p10=tot[len(tot) // 10], step_ms_p50=tot[len(tot) // 2],
                              step_ms_p90=tot[(9 * len(tot)) // 10], out=out.cpu().numpy())
+
+    # Split-BF16 against FP32 at Np = 128 on the same signal, where the channelizer GEMM has twice the taps
+    # (interleaved trials, medians of per-step HIP event times).
+    np128_info = None
+    if "fp32" in forms and "split_bf16" in forms:
+        Np2 = 128
+        w2 = torch.from_numpy(np.hamming(Np2).astype(np.float32)).to(dev)
+        inter2 = torch.empty(Np2 * N, dtype=torch.complex64, device=dev)
+        out2 = torch.empty(Np2, N, dtype=torch.complex64, device=dev)
+        ev2 = {f: [] for f in ("fp32", "split_bf16")}
+        for rep in range(args.warmup + args.steps):
+            for form in ev2:
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record(stream)
+                scd.ssca_stage1(x, Np2, inter2, win=w2, precision=form)
+                e[1].record(stream)
+                scd.ssca_stage2(inter2, N, Np2, out2)
+                e[2].record(stream)
+                if rep >= args.warmup:
+                    ev2[form].append(e)
+        torch.cuda.synchronize()
+        med = lambda v: float(np.median(v))
+        t2 = {f: dict(ms_per_step=round(med([e[0].elapsed_time(e[2]) for e in v]), 5),
+                      pass1_ms=round(med([e[0].elapsed_time(e[1]) for e in v]), 5)) for f, v in ev2.items()}
+        np128_info = {"workload": "the headline signal at Np = 128 (N = 2^20), Hamming window", **t2,
+                      "speedup_split_bf16_vs_fp32": round(t2["fp32"]["ms_per_step"] / t2["split_bf16"]["ms_per_step"], 3)}
+        del inter2, out2
 
     # The cross SCD of x and its delayed copy y(n) = x(n + 5) (Eq. (2)'s two-input form with the paper's
     # time-delay example), one scd_ssca_cross_ex call per step on the same workload.
@@ -560,10 +605,14 @@ def main():
             "fell_back": li["fell_back"], "active_strips": li["active_strips"],
             "recall_vs_full": li["recall_vs_full"], "max_err_vs_oracle": errs.get("learned"),
             "note": "whole scd_ssca_learned call: features, fused MLP + selection kernel, selected strips (asynchronous)"}
+        if "vs_acp_threshold" in li:
+            line["forms"]["learned"]["vs_acp_threshold"] = li["vs_acp_threshold"]
         if "mix" in li:
             line["forms"]["learned"]["mix"] = dict(
                 workload=f"{li['mix']['signals']} held-out signals of the selector recipe at N=2^20, Np={Np}",
                 **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in li["mix"].items()})
+    if np128_info is not None:
+        line["split_bf16_np128"] = np128_info
     if cross_info is not None:
         line["cross"] = cross_info
     if stream_info is not None:
