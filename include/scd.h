@@ -290,7 +290,8 @@ int scd_model_load(const char* path, scd_model** model);
 int scd_mlp_param_count(int Np);
 
 /* Features of each signal: x device [batch] signals of N (power of two in [2^14, 2^20]) at opts->x_stride,
- * feat device [batch][2 Np]. Uses library-owned scratch (16 * Np * 8 KiB). */
+ * feat device [batch][2 Np]. Uses library-owned scratch for the segment periodograms (16 * Np * 4 KiB per
+ * signal, at most 8 signals at a time). */
 int scd_features(const float* x, int64_t N, int Np, const float* win, float* feat, const scd_opts* opts);
 
 /* Labels of each strip of densely packed SCDs S (device [batch][Np][N] complex, as written by scd_ssca):
