@@ -4,10 +4,13 @@
 //   windowed frames into LDS (zero outside [0, P*L)), takes their Np-point DFTs, applies the down-conversion
 //   omega_Np^{(k p L) mod Np} and stores X_T channel-major, xt[k][p], so the pair kernel reads rows.
 //   X_T is at most 256 x 1024 complex (2 MiB) and stays in L2.
-// fam_pair: for channel k and a tile of 16 channels l, forms z[p] = X_T[p][k] conj(X_T[p][l]) (the conjugate
-//   multiplication of Eq. (5)) while loading, takes the P-point DFT of the 16 products in LDS and stores
-//   S[k][l][q] as one contiguous 16*P run (the output stream dominates FAM's HBM traffic). Row k, which all
-//   16 products share, is staged in LDS once, so each thread's global loads are only its rows l. In the power
+// fam_pair: for channel k and a tile of KLT channels l, forms z[p] = X_T[p][k] conj(X_T[p][l]) (the conjugate
+//   multiplication of Eq. (5)) while loading, takes the P-point DFT of the KLT products in LDS and stores
+//   S[k][l][q] as one contiguous KLT*P run (the output stream dominates FAM's HBM traffic). Row k, which all
+//   KLT products share, is staged in LDS once, so each thread's global loads are only its rows l. The LDS
+//   rows carry one float2 of padding per 16 elements (radix-16 stages write 16-element strides), and when
+//   every stage has the same radix each sequence's butterflies stay in one wave, so the stages need no
+//   workgroup barrier. KLT is 16, or 64 for P <= 64 (short transforms: more of them per workgroup). In the power
 //   form it stores only |S|^2 of the bins the paper keeps after its second FFT (Alg. 1), -P/4 <= q_c < P/4, in the
 //   order q = 0..P/4-1, P-P/4..P-1: a quarter of the complex output's bytes.
 #include <type_traits>
@@ -21,7 +24,6 @@ namespace {
 
 constexpr int kChanThreads = 256;
 constexpr int kPairThreads = 256;
-constexpr int kLT = 16;  // channels l per pair workgroup
 
 template <int NP>
 __global__ __launch_bounds__(kChanThreads) void fam_chan_fp32(const float2* __restrict__ x, int L, int P,
@@ -67,18 +69,21 @@ __device__ __forceinline__ float power_rn(float2 v) {
 
 // Rows l come from yt: X_T itself for the auto SCD, y's channelizer output for the cross SCD. CONJ multiplies
 // by Y_T[p][l] itself (the conjugate form) instead of its conjugate.
-template <int P, bool POWER, bool CONJ>
+template <int P, int KLT, bool POWER, bool CONJ>
 __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __restrict__ xt,
                                                              const float2* __restrict__ yt, int Np,
                                                              const float2* __restrict__ tabs,
                                                              void* __restrict__ out, int64_t xtbs,
                                                              int64_t obs) {
   constexpr int TWN = P < 16 ? 16 : P;  // omega_P^e (at least the 16 roots a radix-16 stage may index)
-  __shared__ float2 buf[kLT * P];
+  constexpr int BS = P + P / 16;        // padded LDS row
+  using Lay = LdsLayout<BS, 1, 4>;
+  constexpr bool WAVE = uniform_radix<P, 1>() && 64 % (P / StageRadix<P, 1>::value) == 0;
+  __shared__ float2 buf[KLT * BS];
   __shared__ float2 tw[TWN];
   __shared__ float2 rk[P];  // row k of X_T
   const int tid = threadIdx.x;
-  const int l0 = blockIdx.x * kLT;
+  const int l0 = blockIdx.x * KLT;
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
   yt += blockIdx.z * xtbs;
@@ -95,11 +100,11 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
       if (m < H || m >= P - H)
         __builtin_nontemporal_store(power_rn(v), dst + b * (P / 2) + (m < H ? m : m - P / 2));
     };
-    lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
+    lds_fft<P, KLT, kPairThreads, false, Lay, TWN, WAVE>(buf, tw, tid, ld, st);
   } else {
     float2* dst = static_cast<float2*>(out) + blockIdx.z * obs + (static_cast<int64_t>(k) * Np + l0) * P;
     auto st = [&](int b, int m, float2 v) { st1_nt(dst + b * P + m, v); };
-    lds_fft<P, kLT, kPairThreads, false, LdsLayout<P, 1>, TWN>(buf, tw, tid, ld, st);
+    lds_fft<P, KLT, kPairThreads, false, Lay, TWN, WAVE>(buf, tw, tid, ld, st);
   }
 }
 
@@ -113,21 +118,32 @@ hipError_t chan(const float2* x, int L, int P, const float* win, const float2* t
   return hipGetLastError();
 }
 
+template <int P, int KLT>
+hipError_t pair_tile(const float2* xt, const float2* yt, bool conj, int Np, const float2* tabs, void* out, bool power,
+                     int batch, int64_t obs, hipStream_t s) {
+  dim3 grid(Np / KLT, Np, batch);
+  const int64_t xtbs = static_cast<int64_t>(Np) * P;
+  if (power)
+    hipLaunchKernelGGL((fam_pair_fp32<P, KLT, true, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
+  else if (conj)
+    hipLaunchKernelGGL((fam_pair_fp32<P, KLT, false, true>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
+  else
+    hipLaunchKernelGGL((fam_pair_fp32<P, KLT, false, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
+                       xtbs, obs);
+  return hipGetLastError();
+}
+
+// Channels l per workgroup: 64 for P <= 64 (at most Np), else 16. Np is a power of two >= 16.
 template <int P>
 hipError_t pair(const float2* xt, const float2* yt, bool conj, int Np, const float2* tabs, void* out, bool power,
                 int batch, int64_t obs, hipStream_t s) {
-  dim3 grid(Np / kLT, Np, batch);
-  const int64_t xtbs = static_cast<int64_t>(Np) * P;
-  if (power)
-    hipLaunchKernelGGL((fam_pair_fp32<P, true, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
-                       xtbs, obs);
-  else if (conj)
-    hipLaunchKernelGGL((fam_pair_fp32<P, false, true>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
-                       xtbs, obs);
-  else
-    hipLaunchKernelGGL((fam_pair_fp32<P, false, false>), grid, dim3(kPairThreads), 0, s, xt, yt, Np, tabs, out,
-                       xtbs, obs);
-  return hipGetLastError();
+  if constexpr (P <= 64) {
+    if (Np >= 64) return pair_tile<P, 64>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+    if (Np == 32) return pair_tile<P, 32>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
+  }
+  return pair_tile<P, 16>(xt, yt, conj, Np, tabs, out, power, batch, obs, s);
 }
 
 }  // namespace

@@ -417,9 +417,14 @@ __device__ __forceinline__ void stockham_rest(float2* buf, const float2* tw, int
 // other waves wrote the inputs, and after it before the buffer is reused.
 template <int L, int NS>
 constexpr bool uniform_radix() {
-  if constexpr (NS * StageRadix<L, NS>::value >= L) return true;
-  else return StageRadix<L, NS>::value == StageRadix<L, 1>::value && uniform_radix<L, NS * StageRadix<L, NS>::value>();
+  constexpr int R = StageRadix<L, NS>::value;
+  if constexpr (R != StageRadix<L, 1>::value) return false;
+  else if constexpr (NS * R >= L) return true;
+  else return uniform_radix<L, NS * R>();
 }
+static_assert(uniform_radix<256, 1>() && uniform_radix<16, 1>() && uniform_radix<4, 1>() && !uniform_radix<32, 1>() &&
+                  !uniform_radix<64, 1>() && !uniform_radix<512, 1>() && !uniform_radix<1024, 1>(),
+              "uniform_radix: every stage's radix equals the first's");
 template <int L, int NB, int NT, bool BFAST, class Lay, int TWN = 1024, bool WAVE = false, class LoadF, class StoreF>
 __device__ __forceinline__ void lds_fft(float2* buf, const float2* tw, int tid, LoadF& ld, StoreF& st) {
   static_assert(L >= 2 && L <= 1024 && (L & (L - 1)) == 0, "length must be a power of two in [2, 1024]");
