@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--no-cross", action="store_true", help="skip the cross-SCD and streaming measurements")
     ap.add_argument("--mix-signals", type=int, default=8,
                     help="held-out selector-recipe signals for the learned form's mixed-workload line (0: skip)")
+    ap.add_argument("--combined-signals", type=int, default=64,
+                    help="signals of the combined ragged workload (lengths 2^14..2^20, Np 64/128; 0: skip)")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="processes for the oracle's all-core leg (0: min(16, os.cpu_count()), the host share of one GPU)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -316,6 +318,66 @@ def main():
         results[form] = dict(ms_per_step=ms, pass1_ms=float(np.mean(p1)), pass2_ms=float(np.mean(p2)),
                              step_ms_p10=tot[len(tot) // 10], step_ms_p50=tot[len(tot) // 2],
                              step_ms_p90=tot[(9 * len(tot)) // 10], out=out.cpu().numpy())
+
+    # The combined workload: a ragged batch of signals of lengths 2^U{14..20} with Np = 64 (even index) or 128
+    # (odd), one scd_ssca_batch call each way. Plain FP32 against split-BF16 + learned strips + fallback; the
+    # recall is scored against the labels of the FP32 outputs.
+    combined_info = None
+    if args.combined_signals and "fp32" in forms and "split_bf16" in forms:
+        from paper_2506_18003_amd import selector as SEL2
+
+        models = {}
+        with torch.cuda.device(dev):
+            for n in (64, 128):
+                models[n] = SEL2.Model.load(os.path.join(ROOT, "paper_2506_18003_amd", "models", f"selector_np{n}.scdm"))
+        sigs = [W.cfg5_signal(i) for i in range(args.combined_signals)]
+        xs = [torch.from_numpy(c["x"].astype(np.complex64)).to(dev) for c in sigs]
+        wins = {n: torch.from_numpy(np.asarray(W.sg.hamming(n), np.float32)).to(dev) for n in (64, 128)}
+        outs_f = [torch.empty(c["Np"], c["N"], dtype=torch.complex64, device=dev) for c in sigs]
+        outs_l = [torch.zeros(c["Np"], c["N"], dtype=torch.complex64, device=dev) for c in sigs]
+        items_f = [dict(x=x, Np=c["Np"], win=wins[c["Np"]], out=o) for x, c, o in zip(xs, sigs, outs_f)]
+        items_l = [dict(x=x, Np=c["Np"], win=wins[c["Np"]], out=o, selector=models[c["Np"]])
+                   for x, c, o in zip(xs, sigs, outs_l)]
+        tf, tl, tl32 = [], [], []
+        masks = None
+        for rep in range(1 + 3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            scd.ssca_batch(items_f)
+            e[1].record(stream)
+            res = scd.ssca_batch(items_l, precision="split_bf16")
+            e[2].record(stream)
+            scd.ssca_batch(items_l)
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                tf.append(e[0].elapsed_time(e[1]))
+                tl.append(e[1].elapsed_time(e[2]))
+                tl32.append(e[2].elapsed_time(e[3]))
+            masks = [m for _, m in res]
+        pts = float(sum(c["Np"] * c["N"] for c in sigs))
+        strips = sum(int(m.sum().item()) for m in masks)
+        nstrips = sum(c["Np"] for c in sigs)
+        tp = pos = 0
+        for o, m in zip(outs_f, masks):
+            lab = SEL2.strip_labels(o)[0].cpu().numpy()[0] > 0.5
+            mm = m.cpu().numpy().astype(bool)
+            tp += int((mm & lab).sum())
+            pos += int(lab.sum())
+        fms, lms, l32 = float(np.median(tf)), float(np.median(tl)), float(np.median(tl32))
+        combined_info = {
+            "workload": f"{len(sigs)} signals of lengths 2^U{{14..20}} (cfg-5 recipe), Np 64 (even) / 128 (odd), "
+                        "one scd_ssca_batch call", "scd_pts": pts,
+            "fp32": {"ms_per_batch": round(fms, 4), "pts_per_s": round(pts / (fms * 1e-3), 1)},
+            "split_bf16_learned": {"ms_per_batch": round(lms, 4), "pts_per_s": round(pts / (lms * 1e-3), 1),
+                                   "speedup_vs_fp32": round(fms / lms, 3), "strip_fraction": round(strips / nstrips, 4),
+                                   "recall_vs_fp32_labels": round(tp / max(1, pos), 5),
+                                   "active_fraction": round(pos / nstrips, 4)},
+            "fp32_learned": {"ms_per_batch": round(l32, 4), "pts_per_s": round(pts / (l32 * 1e-3), 1),
+                             "speedup_vs_fp32": round(fms / l32, 3)}}
+        for mdl in models.values():
+            mdl.close()
+        del outs_f, outs_l, items_f, items_l, xs
 
     # Split-BF16 against FP32 at Np = 128 on the same signal, where the channelizer GEMM has twice the taps
     # (interleaved trials, medians of per-step HIP event times).
@@ -613,6 +675,8 @@ def main():
                 **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in li["mix"].items()})
     if np128_info is not None:
         line["split_bf16_np128"] = np128_info
+    if combined_info is not None:
+        line["combined"] = combined_info
     if cross_info is not None:
         line["cross"] = cross_info
     if stream_info is not None:

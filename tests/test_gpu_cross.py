@@ -58,7 +58,8 @@ def test_cross_with_itself_is_the_auto_scd(dev):
 
 
 @pytest.mark.parametrize("conjugate", [False, True])
-@pytest.mark.parametrize("Np,L,P", [(16, 4, 64), (64, 16, 128), (256, 64, 32), (32, 1, 1024), (16, 16, 4)])
+@pytest.mark.parametrize("Np,L,P", [(16, 4, 64), (64, 16, 128), (256, 64, 32), (32, 1, 1024), (16, 16, 4), (32, 8, 64),
+                                    (64, 4, 256)])
 def test_fam_cross_matches_oracle(dev, Np, L, P, conjugate):
     x = sg.bpsk(P * L, 0.06, 6, 2.0, sg.rng_for(103, Np + P)).astype(np.complex64)
     y = sg.msk(P * L, 0.11, 8, 4.0, sg.rng_for(104, Np + P)).astype(np.complex64)

@@ -19,7 +19,7 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("Np,L,P", [(16, 4, 4), (32, 8, 32), (64, 16, 128), (256, 64, 32), (16, 1, 1024)])
+@pytest.mark.parametrize("Np,L,P", [(16, 4, 4), (32, 8, 32), (64, 16, 128), (256, 64, 32), (16, 1, 1024), (64, 8, 256)])
 def test_fam_power_equals_view_of_complex_grid(dev, Np, L, P):
     x = sg.bpsk(P * L, 0.07, 6, 3.0, sg.rng_for(97, Np + P)).astype(np.complex64)
     xt = torch.from_numpy(x).to(dev)

@@ -66,7 +66,10 @@ def test_ssca_sizes(dev, N, Np):
     assert rel(S, ref) <= TOL_FP32
 
 
-@pytest.mark.parametrize("Np,L,P", [(16, 4, 64), (16, 16, 4), (64, 16, 128), (256, 64, 32), (128, 1, 1024)])
+# Pair tiles of 16, 32 and 64 channels (P <= 64 takes min(Np, 64)); single-stage, uniform-radix (wave-local)
+# and mixed-radix transforms.
+@pytest.mark.parametrize("Np,L,P", [(16, 4, 64), (16, 16, 4), (64, 16, 128), (256, 64, 32), (128, 1, 1024),
+                                    (32, 8, 64), (64, 4, 16), (128, 8, 8), (32, 16, 256), (64, 2, 512)])
 def test_fam_sizes(dev, Np, L, P):
     x = sg.qpsk(P * L, 0.07, 6, 3.0, sg.rng_for(51, Np + L + P))
     w = w32(Np)
