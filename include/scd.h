@@ -127,13 +127,16 @@ int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, in
  * before the first block and after the last), in fixed device memory: a library-owned ring of `slots` blocks with
  * Np samples of halo at its two ends, and the caller's output buffers used in rotation. Each push copies one host
  * block on the receiver's own copy stream (default priority) and enqueues the estimate of the previous block on
- * the caller's stream, ordered by events, so the copy of one block overlaps the estimate of an earlier one.
+ * the caller's stream, ordered by events, so the copy of one block overlaps the estimate of an earlier one. The
+ * ring bounds how far the host runs ahead: a push first waits until the estimate of block c + 1 - slots (the
+ * last one reading the slot block c reuses) has finished.
  *
  * scd_receiver_create: N, Np as scd_ssca (N >= Np); win: device Np floats (caller-owned, read by every estimate);
  *   slots in [3, 64] (4 lets a copy overlap the estimate two blocks back); outputs: n_outputs (1..64) device
  *   buffers of Np*N complex values each, caller-owned; stream: hipStream_t of the estimates (NULL: null stream).
  *   Allocates the ring (8 (slots N + 2 Np) bytes) on the current device and synchronises once.
- * scd_receiver_push: host_block holds N complex values, in pinned memory for the copy to be asynchronous; it
+ * scd_receiver_push: waits for the slot (above), then copies; host_block holds N complex values, in pinned
+ *   memory for the copy to be asynchronous; it
  *   must not be modified until its copy has completed (scd_receiver_wait_copy). On return *out_index is the
  *   output buffer that will hold the previous block's estimate in stream order, and *offset that block's first
  *   sample (-1 and unchanged for the first push). A buffer is overwritten n_outputs estimates later.
