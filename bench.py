@@ -515,12 +515,27 @@ def main():
                         "peak_without_packed_fp32": VALU_PEAK_TFLOPS,
                         "frac_without_packed_fp32": round(tfs / VALU_PEAK_TFLOPS, 4)}}
 
+    # The box's own device-to-device copy rate (torch's copy of 512 MiB, read + write), beside the datasheet peak.
+    csrc = torch.empty(64 << 20, dtype=torch.complex64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    ce = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ce[0].record(stream)
+    for _ in range(10):
+        cdst.copy_(csrc)
+    ce[1].record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * csrc.numel() * 8 * 10 / (ce[0].elapsed_time(ce[1]) * 1e-3) / 1e9
+    del csrc, cdst
+
     dom = max(kern, key=lambda k: kern[k][2])
     roof = dict(kernel_roof(dom), kernel=dom, traffic=measured_traffic(dom, digest))
     roof.update({
             "B_2p_frac": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "per_kernel": {k: kernel_roof(k) for k in kern},
+            "measured_copy_GBs": round(copy_gbs, 1),
+            "B_2p_frac_of_measured_copy": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / copy_gbs, 4),
             "source_digest": digest})
 
     fam_line = None
