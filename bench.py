@@ -56,9 +56,9 @@ def source_digest(files=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, digest: str):
+def measured_traffic(kernel: str, digest: str, path: str = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on this source."""
-    path = os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -73,9 +73,13 @@ CALIB_BYTES = 256 << 20          # the --copy-calib kernel reads and writes this
 TRAFFIC_KERNELS = {"ssca_pass1": "ssca_pass1_fp32<64, true, false, false, 0>", "ssca_pass2": "ssca_pass2_fp32"}
 
 
-def write_traffic(fetch_csv: str, write_csv: str) -> dict:
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
+
+
+def write_traffic(fetch_csv: str, write_csv: str, path: str = TRAFFIC_PATH) -> dict:
     """Per-launch HBM bytes of each SSCA kernel from FETCH_SIZE / WRITE_SIZE counter CSVs (KiB per dispatch),
-    each counter scaled by the factor that maps its reading of the calibration kernel to the known size."""
+    each counter scaled by the factor that maps its reading of the calibration kernel to the known size.
+    Written to `path` (the committed summary by default) with the current source digest."""
     import csv
 
     def per_kernel(path):
@@ -86,22 +90,21 @@ def write_traffic(fetch_csv: str, write_csv: str) -> dict:
 
     out = {"source_digest": source_digest(), "calibration": {}, "kernels": {}}
     readings = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        pk = per_kernel(path)
+    for counter, csv_path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        pk = per_kernel(csv_path)
         calib = [v for k, v in pk.items() if "MulFunctor" in k]
         if len(calib) != 1:
-            raise SystemExit(f"{path}: expected one calibration kernel reading")
+            raise SystemExit(f"{csv_path}: expected one calibration kernel reading")
         factor = CALIB_BYTES / calib[0]
         out["calibration"][counter] = {"raw_bytes": calib[0], "known_bytes": CALIB_BYTES, "factor": factor}
         for name, pat in TRAFFIC_KERNELS.items():
             hits = [v for k, v in pk.items() if pat in k]
             if len(hits) != 1:
-                raise SystemExit(f"{path}: expected one {pat} kernel, found {len(hits)}")
+                raise SystemExit(f"{csv_path}: expected one {pat} kernel, found {len(hits)}")
             readings.setdefault(name, {})[counter] = hits[0] * factor
     for name, r in readings.items():
         out["kernels"][name] = {"fetch_bytes": round(r["FETCH_SIZE"]), "write_bytes": round(r["WRITE_SIZE"]),
                                 "bytes_per_launch": round(r["FETCH_SIZE"] + r["WRITE_SIZE"])}
-    path = os.path.join(ROOT, "profiles", "traffic_ssca_n2p20_np64.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
