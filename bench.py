@@ -699,7 +699,7 @@ def main():
             "selected_pts_per_s": round(li["strips"] * N / (li["ms_per_step"] * 1e-3), 1),
             "fell_back": li["fell_back"], "active_strips": li["active_strips"],
             "recall_vs_full": li["recall_vs_full"], "max_err_vs_oracle": errs.get("learned"),
-            "note": "whole scd_ssca_learned call: features, fused MLP + selection kernel, selected strips (asynchronous)"}
+            "note": "whole scd_ssca_learned call: features, MLP + selection kernels, selected strips (asynchronous)"}
         if "vs_acp_threshold" in li:
             line["forms"]["learned"]["vs_acp_threshold"] = li["vs_acp_threshold"]
         if "mix" in li:

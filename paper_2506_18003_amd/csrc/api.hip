@@ -36,6 +36,7 @@ struct DevState {
 // features (2 Np) + standardised features (2 Np) + activations (4 * 256) + logits (Np) + scores (Np) + conf
 constexpr int kSelStructFloats = (sizeof(scd::ChanSel) + 3) / 4 + 4;
 constexpr int kSelScratchFloats = 4 * 256 + 4 * 256 + 2 * 256 + 64 + kSelStructFloats;
+static_assert(2 * 256 + 3 * 256 + 4 * 256 <= kSelScratchFloats - kSelStructFloats - 2, "selector scratch layout");
 std::map<int, DevState> g_dev;
 
 int fail(int code, const char* fmt, ...) {
@@ -798,7 +799,9 @@ int learned_select(const float* x, int64_t N, int Np, const float* win, const sc
   *conf = f + kSelScratchFloats - kSelStructFloats - 2;
   *fell = reinterpret_cast<int*>(*conf + 1);
   *dsel = reinterpret_cast<scd::ChanSel*>(f + kSelScratchFloats - kSelStructFloats);
-  float* act = f + 2 * 256;  // h1, h2 (256 each), then the Np scores
+  // Layout of the selector scratch: features [0, 512), then act: h1 and h2 (256 each) and the Np scores, then
+  // the second layer's 4 x 256 partial sums at act + 768 (up to float 2304), then conf, fell and the ChanSel.
+  float* act = f + 2 * 256;
   *scores = act + 2 * 256;
   const hipError_t e = scd::launch_select_infer(f, selector->mu, selector->sigma, selector->params, Np,
                                                 selector->theta, selector->conf_min, act, mask, *conf, *fell, *dsel,

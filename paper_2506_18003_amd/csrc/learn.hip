@@ -380,19 +380,24 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
   return v;
 }
 
-// Selector inference of one signal in one workgroup of 1024 threads (16 waves), which removes the launches
-// between the layers:
-//   - standardise the raw features: the PSD part is centred over k first, then bf16-round each input;
-//   - three dense layers: wave w computes a block of rows, the lanes reading 64 consecutive weights per load
-//     (whole 256-byte runs); a row is out[o] = act(sum_i bf16(W[o][i]) in[i] + b[o]) with FP32 accumulation in
-//     the order of the lanes' chunks, then a DPP reduction across the wave. The next layer's weights are loaded
-//     before the current layer's arithmetic, so each layer waits for memory about once;
-//   - the selection: mask, confidence min_k max(s_k, 1 - s_k), fallback to every strip below conf_min, and the
-//     channel selection the SSCA kernels read (strip list in increasing k from wave ballots and per-wave
-//     counts, subset and pair lists from the kept strips).
-// The activations (h1, h2 and the Np scores) are also written to act.
+// Selector inference of one signal in two launches of 1024-thread workgroups (16 waves):
+//   - infer_l12_kernel, kInferBlocks workgroups. Each standardises the raw features (the PSD part centred over k
+//     first, then each input rounded to bf16). Workgroup g then computes rows [64 g, 64 g + 64) of the first
+//     layer, and the second layer's partial sums over those same 64 hidden inputs for all 256 of its rows. So
+//     each workgroup's CU fetches a quarter of W1 and of W2, all of its loads issued at once. The cold weights
+//     (the SSCA's traffic evicts them between calls) arrive over four CUs instead of one;
+//   - infer_l3_select_kernel, one workgroup: the second layer's rows from the partials (summed in workgroup
+//     order, then the bias), the third layer, and the selection: mask, confidence min_k max(s_k, 1 - s_k),
+//     fallback to every strip below conf_min, and the channel selection the SSCA kernels read (strip list in
+//     increasing k from wave ballots and per-wave counts, subset and pair lists from the kept strips).
+// A dense row is out[o] = act(sum_i bf16(W[o][i]) in[i] + b[o]) with FP32 accumulation: each lane sums its
+// inputs i = 64 c + lane in order of c, and a DPP reduction sums the lanes. The activations (h1, h2, the Np
+// scores) are also written to act.
 constexpr int kInferThreads = 1024;
 constexpr int kInferWaves = kInferThreads / 64;
+constexpr int kInferBlocks = 4;                     // workgroups of the first launch
+constexpr int kInferRows1 = kHidden / kInferBlocks; // first-layer rows (and second-layer inputs) per workgroup
+static_assert(kInferRows1 == 64 && kInferRows1 % kInferWaves == 0, "one wave-wide chunk of h1 per workgroup");
 
 // One dense layer: wave w owns the NOUT / 16 consecutive rows from w NOUT / 16. Its weights are loaded in
 // batches of RB rows (every load of a batch in flight at once, at most 64 registers), one batch when they fit.
@@ -445,30 +450,30 @@ struct Dense {
 };
 
 template <int NP>
-__global__ __launch_bounds__(kInferThreads) void select_infer_kernel(
-    const float* __restrict__ feat, const float* __restrict__ mu, const float* __restrict__ sigma,
-    const float* __restrict__ params, float theta, float conf_min, float* __restrict__ act,
-    unsigned char* __restrict__ mask, float* __restrict__ conf_out, int* __restrict__ fell,
-    ChanSel* __restrict__ sel) {
+__global__ __launch_bounds__(kInferThreads) void infer_l12_kernel(const float* __restrict__ feat,
+                                                                  const float* __restrict__ mu,
+                                                                  const float* __restrict__ sigma,
+                                                                  const float* __restrict__ params,
+                                                                  float* __restrict__ act, float* __restrict__ part) {
   constexpr int NIN = 2 * NP;
-  constexpr int S = NP / 16;
+  constexpr int C1 = NIN >= 64 ? NIN / 64 : 1;      // first-layer loads per row and lane
+  constexpr int R1 = kInferRows1 / kInferWaves;    // first-layer rows per wave
+  constexpr int R2 = kHidden / kInferWaves;        // second-layer rows per wave
   __shared__ float x0[NIN];
-  __shared__ float bs[2 * kHidden + NP];  // the three layers' biases
-  __shared__ float h1[kHidden];
-  __shared__ float h2[kHidden];
-  __shared__ float sc[NP];
-  __shared__ float red[kInferWaves];
-  __shared__ int wcnt[kInferWaves];
-  __shared__ unsigned long long wbits[kInferWaves];
-  __shared__ unsigned char keep[NP];
-  __shared__ unsigned char used[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ float h1[kInferRows1];
+  __shared__ float red[1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = blockIdx.x;
   const MlpLayout L = mlp_layout(NP);
-  using D1 = Dense<NIN, kHidden>;
-  using D2 = Dense<kHidden, kHidden>;
-  using D3 = Dense<kHidden, NP>;
-  float w1[D1::RB][D1::C];  // the first layer's weights load while the features are standardised
-  D1::load(params + L.W1, 0, w, lane, w1);
+  const bool live = NIN >= 64 || lane < NIN;
+  // Every weight this workgroup needs, in flight while the features are standardised.
+  float w1[R1][C1], w2[R2];
+#pragma unroll
+  for (int u = 0; u < R1; ++u)
+#pragma unroll
+    for (int cc = 0; cc < C1; ++cc)
+      w1[u][cc] = live ? params[L.W1 + static_cast<int64_t>(kInferRows1 * g + R1 * w + u) * NIN + 64 * cc + lane] : 0.f;
+#pragma unroll
+  for (int u = 0; u < R2; ++u) w2[u] = params[L.W2 + static_cast<int64_t>(R2 * w + u) * kHidden + kInferRows1 * g + lane];
   if (w == 0) {
     float ps = 0.f;
     for (int i = lane; i < NP; i += 64) ps += feat[i];
@@ -478,35 +483,68 @@ __global__ __launch_bounds__(kInferThreads) void select_infer_kernel(
   __syncthreads();
   const float mean = red[0];
   for (int i = tid; i < NIN; i += kInferThreads) x0[i] = bf16r((feat[i] - (i < NP ? mean : 0.f) - mu[i]) / sigma[i]);
-  for (int i = tid; i < 2 * kHidden + NP; i += kInferThreads)
-    bs[i] = i < kHidden ? params[L.b1 + i] : i < 2 * kHidden ? params[L.b2 + i - kHidden] : params[L.b3 + i - 2 * kHidden];
   __syncthreads();
-  // The next layer's first batch is issued before the current layer's arithmetic (in flight during it) when
-  // both batches fit in 96 registers; otherwise after it.
-  constexpr bool kPre2 = D1::RB * D1::C + D2::RB * D2::C <= 96;
-  constexpr bool kPre3 = D2::RB * D2::C + D3::RB * D3::C <= 96;
-  float w2[D2::RB][D2::C];
-  if constexpr (kPre2) D2::load(params + L.W2, 0, w, lane, w2);
-  D1::template run<0>(params + L.W1, bs, x0, h1, w, lane, w1);
-  if constexpr (!kPre2) D2::load(params + L.W2, 0, w, lane, w2);
-  __syncthreads();
-  float w3[D3::RB][D3::C];
-  if constexpr (kPre3) D3::load(params + L.W3, 0, w, lane, w3);
-  D2::template run<0>(params + L.W2, bs + kHidden, h1, h2, w, lane, w2);
-  if constexpr (!kPre3) D3::load(params + L.W3, 0, w, lane, w3);
-  __syncthreads();
-  D3::template run<1>(params + L.W3, bs + 2 * kHidden, h2, sc, w, lane, w3);
-  __syncthreads();
-  for (int i = tid; i < kHidden; i += kInferThreads) {
-    act[i] = h1[i];
-    act[kHidden + i] = h2[i];
+  float xv[C1];
+#pragma unroll
+  for (int cc = 0; cc < C1; ++cc) xv[cc] = live ? x0[64 * cc + lane] : 0.f;
+#pragma unroll
+  for (int u = 0; u < R1; ++u) {
+    float acc = 0.f;
+#pragma unroll
+    for (int cc = 0; cc < C1; ++cc) acc = fmaf(bf16r(w1[u][cc]), xv[cc], acc);
+    acc = wave_sum_lane63(acc);
+    const int r = R1 * w + u;
+    if (lane == 63) {
+      const float h = bf16r(fmaxf(acc + params[L.b1 + kInferRows1 * g + r], 0.f));
+      h1[r] = h;
+      act[kInferRows1 * g + r] = h;
+    }
   }
+  __syncthreads();
+  const float hv = h1[lane];
+#pragma unroll
+  for (int u = 0; u < R2; ++u) {
+    const float p = wave_sum_lane63(bf16r(w2[u]) * hv);
+    if (lane == 63) part[g * kHidden + R2 * w + u] = p;
+  }
+}
+
+template <int NP>
+__global__ __launch_bounds__(kInferThreads) void infer_l3_select_kernel(
+    const float* __restrict__ params, const float* __restrict__ part, float theta, float conf_min,
+    float* __restrict__ act, unsigned char* __restrict__ mask, float* __restrict__ conf_out,
+    int* __restrict__ fell, ChanSel* __restrict__ sel) {
+  constexpr int S = NP / 16;
+  __shared__ float b3[NP];
+  __shared__ float h2[kHidden];
+  __shared__ float sc[NP];
+  __shared__ float red[kInferWaves];
+  __shared__ int wcnt[kInferWaves];
+  __shared__ unsigned long long wbits[kInferWaves];
+  __shared__ unsigned char keep[NP];
+  __shared__ unsigned char used[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const MlpLayout L = mlp_layout(NP);
+  using D3 = Dense<kHidden, NP>;
+  float w3[D3::RB][D3::C];  // the third layer's first batch, in flight while the second layer is finished
+  D3::load(params + L.W3, 0, w, lane, w3);
+  if (tid < kHidden) {
+    float acc = part[tid];
+#pragma unroll
+    for (int gg = 1; gg < kInferBlocks; ++gg) acc += part[gg * kHidden + tid];
+    const float h = bf16r(fmaxf(acc + params[L.b2 + tid], 0.f));
+    h2[tid] = h;
+    act[kHidden + tid] = h;
+  }
+  if (tid < NP) b3[tid] = params[L.b3 + tid];
+  __syncthreads();
+  D3::template run<1>(params + L.W3, b3, h2, sc, w, lane, w3);
+  __syncthreads();
   const float s = tid < NP ? sc[tid] : 0.5f;
   if (tid < NP) act[2 * kHidden + tid] = s;
   float c = tid < NP ? fmaxf(s, 1.f - s) : 1.f;
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) c = fminf(c, __shfl_xor(c, m, 64));
-  __syncthreads();  // every wave has read red[0] (the PSD mean) above
   if (lane == 0) red[w] = c;
   __syncthreads();
   float conf = red[0];
@@ -553,8 +591,11 @@ template <int NP>
 hipError_t select_infer(const float* feat, const float* mu, const float* sigma, const float* params, float theta,
                         float conf_min, float* act, unsigned char* mask, float* conf, int* fell, ChanSel* sel,
                         hipStream_t s) {
-  hipLaunchKernelGGL(select_infer_kernel<NP>, dim3(1), dim3(kInferThreads), 0, s, feat, mu, sigma, params, theta,
-                     conf_min, act, mask, conf, fell, sel);
+  float* part = act + 3 * kHidden;  // kInferBlocks x 256 partial sums of the second layer
+  hipLaunchKernelGGL(infer_l12_kernel<NP>, dim3(kInferBlocks), dim3(kInferThreads), 0, s, feat, mu, sigma, params,
+                     act, part);
+  hipLaunchKernelGGL(infer_l3_select_kernel<NP>, dim3(1), dim3(kInferThreads), 0, s, params, part, theta, conf_min,
+                     act, mask, conf, fell, sel);
   return hipGetLastError();
 }
 
