@@ -124,9 +124,11 @@ def ssca_stream(x, N: int, Np: int, win=None):
 class SscaReceiver:
     """Continuous streaming SSCA of blocks of N samples arriving from the host (scd_receiver_* in
     include/scd.h): fixed device memory, a ring of `slots` device blocks owned by the library and `outputs`
-    output tensors owned here and reused in rotation. push(block) copies one pinned complex64 CPU tensor [N] on
-    the receiver's copy stream and enqueues the estimate of the block before it on the current stream; it
-    returns (offset, S [Np, N]) for that block (None for the first). finish() returns the last block's estimate.
+    output tensors owned here and reused in rotation. push(block) waits until the ring slot it reuses is free (the
+    estimate `slots` - 1 blocks back has finished: the ring bounds how far the host runs ahead), copies one
+    pinned complex64 CPU tensor [N] on the receiver's copy stream and enqueues the estimate of the block before it
+    on the current stream; it returns (offset, S [Np, N]) for that block (None for the first). finish() returns
+    the last block's estimate.
     A returned S is overwritten `outputs` estimates later, in stream order: read or copy it before then. A pushed
     host block must not be modified until wait_copy() (or finish()) has returned; this object keeps a reference
     to the last `slots` blocks meanwhile. The estimates equal ssca_block of the whole signal resident on the
