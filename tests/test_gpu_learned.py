@@ -30,7 +30,9 @@ def gpu(x, dev, dtype=torch.complex64):
     return torch.as_tensor(np.ascontiguousarray(x), device=dev).to(dtype)
 
 
-@pytest.mark.parametrize("N,Np", [(1 << 14, 16), (1 << 15, 64), (1 << 14, 256)])
+# The segments start every N/16 samples, so N = 2^20 places them 64 Ki apart; the oracle only reads the 16
+# segments, which keeps the large case cheap.
+@pytest.mark.parametrize("N,Np", [(1 << 14, 16), (1 << 15, 64), (1 << 14, 256), (1 << 20, 64), (1 << 17, 128)])
 def test_features_match_reference(dev, N, Np):
     xs = [sg.bpsk(N, 0.08, 6, 8.0, sg.rng_for(80, N + Np)), sg.noise(N, sg.rng_for(80, 1 + Np))]
     w = sg.hamming(Np).astype(np.float32)
@@ -38,6 +40,17 @@ def test_features_match_reference(dev, N, Np):
     for b, x in enumerate(xs):
         ref = LR.features(f64(x), Np, w.astype(np.float64))
         assert np.abs(F[b] - ref).max() <= 2e-3, b
+
+
+def test_features_batch_spans_launch_chunks(dev):
+    """Ten signals in one call (the features run at most 8 signals per launch): each row equals the feature of its
+    signal computed alone."""
+    N, Np = 1 << 14, 32
+    xs = np.stack([sg.qpsk(N, 0.05 + 0.02 * i, 4 + i, 3.0, sg.rng_for(83, i)) for i in range(10)])
+    w = torch.from_numpy(sg.hamming(Np).astype(np.float32)).to(dev)
+    F = SEL.features(gpu(xs, dev), Np, win=w).cpu().numpy()
+    for i in range(10):
+        assert np.array_equal(F[i], SEL.features(gpu(xs[i], dev), Np, win=w).cpu().numpy()[0]), i
 
 
 def test_labels_match_reference(dev):
