@@ -21,8 +21,8 @@
  *   - Return 0 (SCD_OK) on success, or a negative SCD_ERR_* code; scd_last_error() then gives a message.
  *     Argument errors are detected before any GPU work is enqueued. On error, out is unspecified and x and
  *     win are never written. Nothing is printed and no C++ exception crosses the ABI.
- *   - The library's own device memory (FP64-generated tables, the SSCA intermediate) is allocated on
- *     first use per device and released by scd_shutdown().
+ *   - The library's own device memory is allocated on first use and released by scd_shutdown(): the
+ *     FP64-generated tables per device, and the scratch (SSCA intermediate and the like) per (device, stream).
  */
 #ifndef SCD_H
 #define SCD_H
@@ -96,9 +96,10 @@ typedef struct scd_opts {
  *   win  device, Np floats
  *   out  device, Np*N complex values, row-major [Np][N]
  * Errors: SCD_ERR_NULL, SCD_ERR_SIZE, SCD_ERR_ALIAS, SCD_ERR_PTR, SCD_ERR_NOMEM, SCD_ERR_HIP.
- * Uses a library-owned intermediate of 8*Np*N bytes when N > 1024. That buffer is shared by every call
- * on the device that passes no workspace, and a small per-(N, Np) scratch holding the window's channel-subset
- * forms is shared by every call: calls on one device must not run concurrently on different streams.
+ * Uses a library-owned intermediate of 8*Np*N bytes when N > 1024 and no workspace is given. The library's
+ * scratch (this intermediate, the split-precision operands, the selector's buffers) is kept per (device,
+ * stream): calls on different streams may run concurrently, and calls on one stream are ordered by it. Each
+ * stream's scratch persists until scd_shutdown. The FP64 tables are shared, read-only once built.
  */
 int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out);
 

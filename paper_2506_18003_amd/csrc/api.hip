@@ -22,16 +22,21 @@ thread_local std::string g_err;
 std::mutex g_mu;
 hipStream_t g_stream = nullptr;
 
-struct DevState {
-  std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables + window scratch
-  void* work = nullptr;
+// Library scratch of one stream: only work enqueued on that stream touches it, so calls on different streams
+// never share writable memory.
+struct Scratch {
+  void* work = nullptr;  // SSCA intermediates / FAM X_T
   size_t work_bytes = 0;
   void* aux = nullptr;  // 16-bit copies of x and MFMA weights of the split-precision channelizer
   size_t aux_bytes = 0;
-  void* lrn = nullptr;  // segment SSCAs of the selector features
+  void* lrn = nullptr;  // segment periodograms of the selector features
   size_t lrn_bytes = 0;
-  void* sel = nullptr;  // selector scratch: features, activations, scores, confidence
+  void* sel = nullptr;  // selector scratch: features, activations, scores, confidence, channel selection
   size_t sel_bytes = 0;
+};
+struct DevState {
+  std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables (read-only once built)
+  std::map<hipStream_t, Scratch> streams;
 };
 // features (2 Np) + standardised features (2 Np) + activations (4 * 256) + logits (Np) + scores (Np) + conf
 constexpr int kSelStructFloats = (sizeof(scd::ChanSel) + 3) / 4 + 4;
@@ -120,16 +125,16 @@ int get_tables(DevState& st, int64_t n, int Np, hipStream_t s, float2** out) {
   return SCD_OK;
 }
 
-// Library-owned device buffer of at least `bytes`, grown on demand (the old one is freed after the device
-// drains, since queued kernels may still use it).
-int grow(void** buf, size_t* have, size_t bytes, void** out) {
+// Library-owned device buffer of at least `bytes` for work on `stream`, grown on demand (the old one is freed
+// once the stream drains, since its queued kernels may still use it).
+int grow(void** buf, size_t* have, size_t bytes, hipStream_t stream, void** out) {
   if (bytes == 0) {
     *out = nullptr;
     return SCD_OK;
   }
   if (*have < bytes) {
     if (*buf) {
-      hipError_t e = hipDeviceSynchronize();
+      hipError_t e = hipStreamSynchronize(stream);
       if (e != hipSuccess) return hip_fail(e, "synchronise before workspace growth");
       (void)hipFree(*buf);
       *buf = nullptr;
@@ -147,9 +152,22 @@ int grow(void** buf, size_t* have, size_t bytes, void** out) {
   return SCD_OK;
 }
 
-int get_work(DevState& st, size_t bytes, void** out) { return grow(&st.work, &st.work_bytes, bytes, out); }
-int get_aux(DevState& st, size_t bytes, void** out) { return grow(&st.aux, &st.aux_bytes, bytes, out); }
-int get_lrn(DevState& st, size_t bytes, void** out) { return grow(&st.lrn, &st.lrn_bytes, bytes, out); }
+int get_work(DevState& st, hipStream_t s, size_t bytes, void** out) {
+  Scratch& c = st.streams[s];
+  return grow(&c.work, &c.work_bytes, bytes, s, out);
+}
+int get_aux(DevState& st, hipStream_t s, size_t bytes, void** out) {
+  Scratch& c = st.streams[s];
+  return grow(&c.aux, &c.aux_bytes, bytes, s, out);
+}
+int get_lrn(DevState& st, hipStream_t s, size_t bytes, void** out) {
+  Scratch& c = st.streams[s];
+  return grow(&c.lrn, &c.lrn_bytes, bytes, s, out);
+}
+int get_sel(DevState& st, hipStream_t s, size_t bytes, void** out) {
+  Scratch& c = st.streams[s];
+  return grow(&c.sel, &c.sel_bytes, bytes, s, out);
+}
 
 int current_device(int* dev) {
   hipError_t e = hipGetDevice(dev);
@@ -304,7 +322,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
                                          static_cast<int>(xlen), static_cast<int>(xoff));
     }
     void* aux = nullptr;
-    if (get_aux(st, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
+    if (get_aux(st, r.stream, scd::ssca_mfma_scratch_bytes(n, Np, nb), &aux)) return hipErrorOutOfMemory;
     return scd::launch_ssca_pass1_mfma(prec, xs, n, Np, win, tabs, aux, T, nb, r.xs, tbs, sel, r.stream);
   };
   hipError_t e = hipSuccess;
@@ -327,7 +345,7 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     void* work = r.work;
     if (work) {
       chunk = static_cast<int>(std::min<size_t>(r.batch, r.work_bytes / per));
-    } else if ((rc = get_work(st, per * r.batch, &work))) {
+    } else if ((rc = get_work(st, r.stream, per * r.batch, &work))) {
       return rc;
     }
     float2* T = static_cast<float2*>(work);
@@ -418,7 +436,7 @@ int fam_common(const float* x, int Np, int L, int P, const float* win, float* ou
   int chunk = r.batch;
   void* work = r.work;
   if (work) chunk = static_cast<int>(std::min<size_t>(r.batch, r.work_bytes / per));
-  else if ((rc = get_work(st, per * r.batch, &work))) return rc;
+  else if ((rc = get_work(st, r.stream, per * r.batch, &work))) return rc;
   const float2* xc = reinterpret_cast<const float2*>(x);
   for (int b0 = 0; b0 < r.batch; b0 += chunk) {
     const int nb = std::min(chunk, r.batch - b0);
@@ -664,7 +682,7 @@ int features_impl(const float* x, int64_t N, int Np, const float* win, float* fe
   const int chunk = batch < kFeatChunk ? batch : kFeatChunk;
   const size_t pb = 4u * 16u * static_cast<size_t>(Np) * 1024u * static_cast<size_t>(chunk);
   void* lrn;
-  if ((rc = get_lrn(st, pb, &lrn))) return rc;
+  if ((rc = get_lrn(st, stream, pb, &lrn))) return rc;
   float* P = static_cast<float*>(lrn);
   const float2* xc = reinterpret_cast<const float2*>(x);
   hipError_t e = hipSuccess;
@@ -791,7 +809,7 @@ int learned_select(const float* x, int64_t N, int Np, const float* win, const sc
     if ((rc = check_device_range(x, 8u * static_cast<size_t>(N), "x"))) return rc;
     if ((rc = check_device_range(win, 4u * Np, "win"))) return rc;
     void* p;
-    if ((rc = grow(&g_dev[dev].sel, &g_dev[dev].sel_bytes, 4u * kSelScratchFloats, &p))) return rc;
+    if ((rc = get_sel(g_dev[dev], stream, 4u * kSelScratchFloats, &p))) return rc;
     f = static_cast<float*>(p);
     // Raw features: the first MLP layer centres the PSD part itself.
     if ((rc = features_impl(x, N, Np, win, f, 1, N, stream, false))) return rc;
@@ -892,10 +910,12 @@ void scd_shutdown(void) {
     (void)hipSetDevice(kv.first);
     (void)hipDeviceSynchronize();
     for (auto& p : kv.second.plans) (void)hipFree(p.second);
-    if (kv.second.work) (void)hipFree(kv.second.work);
-    if (kv.second.aux) (void)hipFree(kv.second.aux);
-    if (kv.second.lrn) (void)hipFree(kv.second.lrn);
-    if (kv.second.sel) (void)hipFree(kv.second.sel);
+    for (auto& sc : kv.second.streams) {
+      if (sc.second.work) (void)hipFree(sc.second.work);
+      if (sc.second.aux) (void)hipFree(sc.second.aux);
+      if (sc.second.lrn) (void)hipFree(sc.second.lrn);
+      if (sc.second.sel) (void)hipFree(sc.second.sel);
+    }
   }
   (void)hipSetDevice(cur);
   g_dev.clear();
