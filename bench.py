@@ -14,8 +14,9 @@ same signal, on every core of the host's share (a process pool over strips) and 
 result also gives the error of every GPU form. A `fam` object times the FFT accumulation method on the batch
 workload (16 signals of 16384 samples, Np = 256, L = 64, P = 256), a `fam_paper` object on the paper's own
 FAM workload (N = 2048, Np = 256, L = 64, P = 32) as ms per estimate and input samples per second, both in
-complex and power form. A `cross` object times the cross SCD of the headline signal and its delayed copy, and
-a `stream` object the steady-state time per block of a stream of host blocks (copies included).
+complex and power form. A `cross` object times the cross SCD of the headline signal and its delayed copy, a
+`shard` object one GPU's share of the headline SSCA when its strips are split over 2, 4 or 8 GPUs, and a
+`stream` object the steady-state time per block of a stream of host blocks (copies included).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--forms fp32,...] [--no-cpu-baseline] [--no-fam]
                        [--no-cross] [--cpu-workers W]
@@ -129,6 +130,18 @@ def counter_table(paths) -> str:
             v = acc[k][c]
             lines.append(f"| {short} | {c} | {len(v)} | {sum(v) / len(v):.6g} |")
     return "\n".join(lines)
+
+
+def shard_strips(Np: int, G: int, r: int) -> list:
+    """Strips GPU r of G owns when the SSCA is split by strips: whole channel subsets (k = c mod Np/16) while
+    G <= Np/16, so that no Stage 1 work is repeated; beyond that, half (or smaller) runs of one subset."""
+    S = Np // 16
+    if G <= S:
+        return [k for k in range(Np) if (k % S) % G == r]
+    per = Np // G
+    ks = [k for k in range(Np) if k % S == r % S]
+    h = r // S
+    return ks[h * per:(h + 1) * per]
 
 
 def _oracle_strips(args):
@@ -430,6 +443,29 @@ def main():
                       "speedup_vs_fp32_auto": round(results["fp32"]["ms_per_step"] / cms, 3)}
         del yd
 
+    # One GPU's share of the headline estimate when its strips are split over G GPUs: scd_ssca_strips with the
+    # strips GPU 0 would own. The broadcast of x to the other GPUs and any gather of the output are not in it.
+    shard_info = None
+    if "fp32" in forms and not args.no_cross:
+        shard_info = {"workload": "GPU 0's strips of the headline SSCA split over G GPUs (whole channel subsets "
+                                  "while G <= Np/16, half subsets beyond), scd_ssca_strips; x broadcast and output "
+                                  "gather not included"}
+        for G in (2, 4, 8):
+            ks = shard_strips(Np, G, 0)
+            for _ in range(args.warmup):
+                scd.ssca_strips(x, Np, ks, win=win, out=out)
+            sev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            for i in range(args.steps):
+                sev[i][0].record(stream)
+                scd.ssca_strips(x, Np, ks, win=win, out=out)
+                sev[i][1].record(stream)
+            torch.cuda.synchronize()
+            sms = float(np.median([e[0].elapsed_time(e[1]) for e in sev]))
+            shard_info[f"G{G}"] = {"strips": len(ks), "ms": round(sms, 5),
+                                   "pts_per_s": round(len(ks) * N / (sms * 1e-3), 1),
+                                   "ms_vs_full_over_G": round(sms / (results["fp32"]["ms_per_step"] / G), 3)}
+
     # Streaming: a continuous stream of 2^20-sample blocks pushed from pinned host memory through SscaReceiver
     # (a fixed ring of 4 device slots and 2 reused output buffers; copy and estimate overlapped on two streams).
     # The initiation interval includes the host-to-device copies (PCIe), so it is reported beside `value`, never
@@ -712,6 +748,8 @@ def main():
         line["combined"] = combined_info
     if cross_info is not None:
         line["cross"] = cross_info
+    if shard_info is not None:
+        line["shard"] = shard_info
     if stream_info is not None:
         line["stream"] = stream_info
     print(json.dumps(line), flush=True)

@@ -123,6 +123,22 @@ int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, in
                       const scd_opts* opts);
 
 /*
+ * scd_ssca_strips - the SSCA restricted to a caller-given set of strips. Each strip k of Eq. (7) is its own
+ * N-point DFT of the channel-data product of channel k (Eq. (6)), so any set of strips is computed exactly
+ * and independently of the others. This is one GPU's share when the strips are split over several GPUs.
+ *   strips   host, nstrips distinct strip indices in [0, Np), in any order; read before the call returns
+ *   nstrips  0 .. Np; 0 does nothing (SCD_OK once x, win and out are non-NULL)
+ * Only the listed rows of out ([Np][N] per signal) are written; the other rows are left untouched. Every
+ * signal of a batch gets the same strips. Stage 1 computes each channel subset (strips k = c mod Np/16) that
+ * holds a listed strip; Stage 2 runs only for the listed strips. Precision SCD_FP32 or SCD_SPLIT_BF16
+ * (SCD_ERR_UNSUPPORTED otherwise). Other arguments, options (batch, strides, stream, workspace) and errors as
+ * scd_ssca_ex. A strip outside [0, Np), or listed twice, or nstrips outside [0, Np] gives SCD_ERR_SIZE;
+ * strips == NULL with nstrips > 0 gives SCD_ERR_NULL.
+ */
+int scd_ssca_strips(const float* x, int64_t N, int Np, const float* win, const int* strips, int nstrips, float* out,
+                    const scd_opts* opts);
+
+/*
  * Streaming receiver: SSCA estimates of a continuous stream of host blocks of N samples (the block form of
  * scd_ssca_block_ex over consecutive blocks, each with its true neighbouring samples at its edges; zeros only
  * before the first block and after the last), in fixed device memory: a library-owned ring of `slots` blocks with

@@ -95,6 +95,28 @@ def ssca(x, Np: int, win=None, precision="fp32", out=None, workspace=None):
     return out
 
 
+def ssca_strips(x, Np: int, strips, win=None, precision="fp32", out=None, workspace=None):
+    """SSCA of each signal in x restricted to the listed strips (distinct k in [0, Np)); only those rows of out
+    are written. One GPU's share of an SSCA split by strips; see scd_ssca_strips in include/scd.h."""
+    torch = _torch()
+    _check_x(x)
+    N = x.shape[-1]
+    B = 1 if x.dim() == 1 else x.shape[0]
+    w = _window(win, Np, x.device)
+    shape = (Np, N) if x.dim() == 1 else (B, Np, N)
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.complex64, device=x.device)
+    elif tuple(out.shape) != shape or out.dtype != torch.complex64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous complex64 tensor of shape {shape}")
+    ks = np.ascontiguousarray(np.asarray(list(strips), dtype=np.int32).reshape(-1))
+    xs = x.stride(0) if x.dim() == 2 else 0
+    o = _opts(x, precision, B, xs, Np * N, workspace)
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.lib().scd_ssca_strips(x.data_ptr(), N, Np, w.data_ptr(), ks.ctypes.data, int(ks.size),
+                                              out.data_ptr(), ctypes.byref(o)))
+    return out
+
+
 def ssca_block(x, offset: int, N: int, Np: int, win=None, out=None, workspace=None):
     """SSCA of the block [offset, offset + N) of the signal x ([len] complex64), with frames at the block's
     edges reading the neighbouring samples; see scd_ssca_block_ex."""

@@ -78,6 +78,8 @@ _SIGS = {
                                          ctypes.POINTER(ScdOpts)]),
     "scd_ssca_cross_ex": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, _P, ctypes.c_int, _P,
                                          ctypes.POINTER(ScdOpts)]),
+    "scd_ssca_strips": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.c_int, _P,
+                                       ctypes.POINTER(ScdOpts)]),
     "scd_ssca_stage1_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P, ctypes.POINTER(ScdOpts)]),
     "scd_ssca_stage2_ex": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(ScdOpts)]),
     "scd_fam": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]),

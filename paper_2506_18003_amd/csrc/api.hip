@@ -254,13 +254,27 @@ namespace {
 
 enum class SscaPart { kWhole, kStage1, kStage2 };
 
+// Writes a host-built selection to device memory. It travels as a kernel argument, which the runtime copies at
+// launch, so the call needs no separate host-to-device copy and never waits on the host.
+__global__ void put_chansel_kernel(scd::ChanSel sel, scd::ChanSel* dst) {
+  if (threadIdx.x == 0) *dst = sel;
+}
+
+unsigned pow2_at_least(unsigned v) {
+  unsigned p = 1;
+  while (p < v) p <<= 1;
+  return v == 0 ? 0 : p;
+}
+
 // Shared validation and dispatch of the SSCA entry points. For kStage1 `in` is x and `dst` the intermediate;
 // for kStage2 `in` is the intermediate and `dst` the output (win unused); for kWhole `in` is x and `dst` out.
 // ymode: 0 the auto SCD; 1 the cross SCD of `in` and y; 2 the conjugate form (whole transform, FP32 only).
 // xlen/xoff (whole transform, FP32): the block [xoff, xoff + N) of a signal of xlen samples; 0 = the signal.
+// upload (whole transform): a host-built selection, copied into the stream's selector scratch once every argument
+// has been checked; selp then gives only the grid sizes.
 int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* win, float* dst,
                 const scd_opts* opts, const scd::SelArg* selp = nullptr, const float* y = nullptr, int ymode = 0,
-                int64_t xlen = 0, int64_t xoff = 0) {
+                int64_t xlen = 0, int64_t xoff = 0, const scd::ChanSel* upload = nullptr) {
   const bool need_win = part != SscaPart::kStage2;
   if (!in || !dst || (need_win && !win)) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
   if (ymode != 0 && !y) return fail(SCD_ERR_NULL, "y must be non-NULL");
@@ -313,7 +327,14 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
   float2* oc = reinterpret_cast<float2*>(dst);
   const int n = static_cast<int>(N);
   const int prec = r.precision;
-  const scd::SelArg sel = selp ? *selp : scd::selarg_all(Np);
+  scd::SelArg sel = selp ? *selp : scd::selarg_all(Np);
+  if (upload) {
+    void* p;
+    if ((rc = get_sel(st, r.stream, 4u * kSelScratchFloats, &p))) return rc;
+    auto* d = reinterpret_cast<scd::ChanSel*>(static_cast<float*>(p) + kSelScratchFloats - kSelStructFloats);
+    hipLaunchKernelGGL(put_chansel_kernel, dim3(1), dim3(64), 0, r.stream, *upload, d);
+    sel.dev = d;
+  }
   // Stage 1 in the requested precision, for nb signals.
   auto stage1 = [&](const float2* xs, float2* T, int nb, int64_t tbs) -> hipError_t {
     if (prec == SCD_FP32) {
@@ -337,9 +358,21 @@ int ssca_common(SscaPart part, const float* in, int64_t N, int Np, const float* 
     } else {
       e = scd::launch_ssca_pass2(ic, n, Np, tabs, oc, r.batch, r.xs, r.os, sel, r.stream);
     }
-  } else if (per == 0) {
+  } else if (per == 0 && !upload) {
     // N == 1024: the Stage 1 output is the final result.
     e = stage1(ic, oc, r.batch, r.os);
+  } else if (per == 0) {
+    // N == 1024 with a host selection: Stage 1 writes whole channel subsets, so it goes to the library's buffer
+    // (whose layout at M2 = 1 is the output's) and only the listed rows are copied out.
+    const size_t row = 8u * static_cast<size_t>(N);
+    void* work;
+    if ((rc = get_work(st, r.stream, 8u * static_cast<size_t>(grid) * r.batch, &work))) return rc;
+    float2* T = static_cast<float2*>(work);
+    e = stage1(ic, T, r.batch, grid);
+    for (int b = 0; b < r.batch && e == hipSuccess; ++b)
+      for (int i = 0; i < upload->nch && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(oc + b * r.os + upload->ch[i] * N, T + b * grid + upload->ch[i] * N, row,
+                           hipMemcpyDeviceToDevice, r.stream);
   } else {
     int chunk = r.batch;
     void* work = r.work;
@@ -377,6 +410,45 @@ int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, in
                       const scd_opts* opts) {
   if (len <= 0) return fail(SCD_ERR_SIZE, "len must be positive");
   return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts, nullptr, nullptr, 0, len, offset);
+}
+
+int scd_ssca_strips(const float* x, int64_t N, int Np, const float* win, const int* strips, int nstrips, float* out,
+                    const scd_opts* opts) {
+  if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", Np);
+  if (nstrips < 0 || nstrips > Np) return fail(SCD_ERR_SIZE, "nstrips = %d must lie in [0, Np = %d]", nstrips, Np);
+  if (nstrips > 0 && !strips) return fail(SCD_ERR_NULL, "strips must be non-NULL");
+  if (opts && opts->precision != SCD_FP32 && opts->precision != SCD_SPLIT_BF16)
+    return fail(SCD_ERR_UNSUPPORTED, "a strip list runs in FP32 or split-BF16");
+  // The selection: the listed strips for Stage 2 (ascending), the channel subsets (strips k = c mod Np/16) and
+  // subset pairs (c, c + Np/32) that hold one of them for Stage 1.
+  const int S = Np / 16;
+  scd::ChanSel cs{};
+  for (int i = 0; i < nstrips; ++i) {
+    const int k = strips[i];
+    if (k < 0 || k >= Np) return fail(SCD_ERR_SIZE, "strip %d lies outside [0, %d)", k, Np);
+    if (cs.keep[k >> 5] & (1u << (k & 31))) return fail(SCD_ERR_SIZE, "strip %d is listed twice", k);
+    cs.keep[k >> 5] |= 1u << (k & 31);
+  }
+  bool used[16] = {};
+  for (int k = 0; k < Np; ++k) {
+    if (cs.keep[k >> 5] & (1u << (k & 31))) {
+      cs.ch[cs.nch++] = static_cast<unsigned char>(k);
+      used[k % S] = true;
+    }
+  }
+  for (int c = 0; c < S; ++c)
+    if (used[c]) cs.sub[cs.nsub++] = static_cast<unsigned char>(c);
+  for (int c = 0; c < S / 2; ++c)
+    if (used[c] || used[c + S / 2]) cs.pair[cs.npair++] = static_cast<unsigned char>(c);
+  if (cs.nch == 0) {
+    if (!x || !win || !out) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
+    return SCD_OK;
+  }
+  // Grid sizes: the unit counts rounded up to powers of two (one Stage-1 block mapping needs that); the blocks
+  // past the selection's own counts exit at once.
+  const scd::SelArg sel{nullptr, static_cast<int>(pow2_at_least(cs.nsub)), static_cast<int>(pow2_at_least(cs.npair)),
+                        cs.nch};
+  return ssca_common(SscaPart::kWhole, x, N, Np, win, out, opts, &sel, nullptr, 0, 0, 0, &cs);
 }
 
 int scd_ssca(const float* x, int64_t N, int Np, const float* win, float* out) {

@@ -207,6 +207,17 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   float2* xb = buf + half * kXchgFloats;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    if constexpr (SEL && !PAIR) {
+      // Stage 2 reads only selected strips: a half whose eight strips k = c + S (8 h + kk) are all unselected is
+      // skipped by the whole workgroup (c is uniform).
+      unsigned any = 0;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = c + S * (8 * h + kk);
+        any |= sel->keep[k >> 5] >> (k & 31);
+      }
+      if (!(any & 1u)) continue;
+    }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
@@ -399,7 +410,9 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
   if constexpr (NP >= 32) {
     const int64_t single_blocks = static_cast<int64_t>(M2) * sel.nsub * batch;
     const int64_t pair_blocks = static_cast<int64_t>(M2) * sel.npair * batch;
-    if (single_blocks < kSingleMinBlocks && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
+    // A pair computes both its subsets, so a selection that leaves pairs half used runs single subsets.
+    const bool pairs_full = sel.nsub >= 2 * sel.npair;
+    if (pairs_full && single_blocks < kSingleMinBlocks && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
     else launch(std::false_type{});
   } else {
     launch(std::false_type{});

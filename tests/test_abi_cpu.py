@@ -309,3 +309,27 @@ def test_receiver_rejects_bad_arguments(L):
     assert L.scd_receiver_finish(None, None, None) == _lib.SCD_ERR_NULL
     assert L.scd_receiver_wait_copy(None) == _lib.SCD_ERR_NULL
     assert L.scd_receiver_destroy(None) == 0
+
+
+def test_ssca_strips_rejects_bad_strip_lists(L):
+    def call(ks, n=None, N=1024, Np=32, o=_fake(O)):
+        arr = (ctypes.c_int * max(1, len(ks)))(*ks)
+        return L.scd_ssca_strips(_fake(X), N, Np, _fake(W), arr, len(ks) if n is None else n, o, None)
+    assert call([0, 32]) == _lib.SCD_ERR_SIZE  # outside [0, Np)
+    assert call([-1]) == _lib.SCD_ERR_SIZE
+    assert call([3, 5, 3]) == _lib.SCD_ERR_SIZE  # listed twice
+    assert call([0], n=33) == _lib.SCD_ERR_SIZE  # more strips than Np
+    assert call([0], n=-1) == _lib.SCD_ERR_SIZE
+    assert L.scd_ssca_strips(_fake(X), 1024, 32, _fake(W), None, 2, _fake(O), None) == _lib.SCD_ERR_NULL
+    assert call([], n=0) == 0  # nothing to compute
+    assert call([], n=0, o=None) == _lib.SCD_ERR_NULL
+    # the checks of scd_ssca_ex still apply, before any GPU work
+    assert call([1], N=1000) == _lib.SCD_ERR_SIZE
+    assert call([1], Np=48) == _lib.SCD_ERR_SIZE
+    assert call([1], o=_fake(X + 64)) == _lib.SCD_ERR_ALIAS
+    assert call([1], o=None) == _lib.SCD_ERR_NULL
+    o = _lib.ScdOpts()
+    o.precision = _lib.PRECISIONS["split_fp16"]
+    arr = (ctypes.c_int * 1)(1)
+    assert L.scd_ssca_strips(_fake(X), 1024, 32, _fake(W), arr, 1, _fake(O), ctypes.byref(o)) == \
+        _lib.SCD_ERR_UNSUPPORTED

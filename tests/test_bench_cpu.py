@@ -100,3 +100,15 @@ def test_oracle_pool_leg_equals_single_process(bench):
     S2, _ = bench.cpu_oracle_ssca(x, 16, w, 2)
     assert np.array_equal(S1, S2)
     assert np.abs(S1 - O.ssca(x, 16, w)).max() <= 1e-9 * np.abs(S1).max()
+
+
+@pytest.mark.parametrize("Np,G", [(64, 1), (64, 2), (64, 4), (64, 8), (128, 8), (256, 16), (32, 4)])
+def test_shard_strips_partition_the_strips(bench, Np, G):
+    shards = [bench.shard_strips(Np, G, r) for r in range(G)]
+    assert sorted(k for sh in shards for k in sh) == list(range(Np))
+    assert all(len(sh) == Np // G for sh in shards)
+    S = Np // 16
+    if G <= S:  # whole subsets: no subset is split over two GPUs
+        for sh in shards:
+            subsets = {k % S for k in sh}
+            assert all(k in sh for c in subsets for k in range(c, Np, S))
