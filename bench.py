@@ -569,6 +569,11 @@ def main():
 
     dom = max(kern, key=lambda k: kern[k][2])
     roof = dict(kernel_roof(dom), kernel=dom, traffic=measured_traffic(dom, digest))
+    if roof["traffic"] is not None:
+        # the HBM bytes the kernel really moves (its counters, scaled per launch) at this run's duration
+        tgbs = roof["traffic"] / (kern[dom][2] * 1e-3) / 1e9
+        roof.update({"traffic_GBs": round(tgbs, 1), "traffic_frac_of_peak": round(tgbs / HBM_PEAK_GBS, 4),
+                     "traffic_frac_of_measured_copy": round(tgbs / copy_gbs, 4)})
     roof.update({
             "B_2p_frac": round((8 * N + 3 * 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "B_min_frac": round((8 * N + 8 * Np * N) / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
