@@ -133,7 +133,8 @@ int scd_ssca_block_ex(const float* x, int64_t len, int64_t offset, int64_t N, in
  * holds a listed strip; Stage 2 runs only for the listed strips. Precision SCD_FP32 or SCD_SPLIT_BF16
  * (SCD_ERR_UNSUPPORTED otherwise). Other arguments, options (batch, strides, stream, workspace) and errors as
  * scd_ssca_ex. A strip outside [0, Np), or listed twice, or nstrips outside [0, Np] gives SCD_ERR_SIZE;
- * strips == NULL with nstrips > 0 gives SCD_ERR_NULL.
+ * strips == NULL with nstrips > 0 gives SCD_ERR_NULL. At N = 1024, where Stage 1 alone is the transform, its
+ * output goes through the library's scratch (8*Np*N bytes per signal) and the listed rows are copied to out.
  */
 int scd_ssca_strips(const float* x, int64_t N, int Np, const float* win, const int* strips, int nstrips, float* out,
                     const scd_opts* opts);
