@@ -130,3 +130,16 @@ def test_strips_reject_other_precisions(dev):
     for prec in ("split_fp16", "bf16"):
         with pytest.raises(scd.ScdError):
             scd.ssca_strips(x, 64, [1, 2], precision=prec)
+
+
+def test_strips_batch_through_a_small_workspace(dev):
+    """Three signals through a caller workspace that holds one intermediate (three chunks), with a selection."""
+    N, Np = 1 << 15, 64
+    ks = [2, 6, 33, 63]
+    x = _x(N, 6, dev, batch=3)
+    ws = torch.empty(Np * N, dtype=torch.complex64, device=dev)
+    full = scd.ssca(x, Np)
+    sentinel = torch.full((3, Np, N), complex(0.5, -0.5), dtype=torch.complex64, device=dev)
+    out = scd.ssca_strips(x, Np, ks, out=sentinel.clone(), workspace=ws)
+    torch.cuda.synchronize()
+    _check_rows(out, full, sentinel, ks)
