@@ -379,7 +379,11 @@ typedef struct scd_ssca_item {
 /* SSCA of n signals of any lengths and channel counts, enqueued in item order on one stream (a library form
  * for mixed workloads; the paper estimates one signal at a time). An item without a selector runs as
  * scd_ssca_ex; an item with one runs as scd_ssca_learned with fell_back NULL, so the call never waits for the
- * GPU. Every item uses opts' precision, stream and workspace. opts->batch must be 0 or 1 and both strides 0:
+ * GPU. The selectors of learned items run on two library-owned side streams (default priority) ordered by
+ * events, so the selector of one item overlaps the SSCA of the one before; each item's outputs equal those of
+ * its single call. The side streams start after the work already on opts' stream, and that stream waits for
+ * them, so the results are ordered on it as for single calls. Batch calls on one process run one at a time on
+ * the host. Every item uses opts' precision, stream and workspace. opts->batch must be 0 or 1 and both strides 0:
  * each item is one signal. A caller workspace must hold the largest item's intermediate; the library-owned one
  * grows to it, waiting for the device once when it grows. The call stops at the first item that fails and
  * returns that item's error code, with the item's index in scd_last_error; the items before it stay enqueued.

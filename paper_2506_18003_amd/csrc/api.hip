@@ -34,10 +34,20 @@ struct Scratch {
   void* sel = nullptr;  // selector scratch: features, activations, scores, confidence, channel selection
   size_t sel_bytes = 0;
 };
+// Streams and events of the batch pipeline (scd_ssca_batch): the selectors of learned items run on two side
+// streams, each with its own scratch, so the selector of one item overlaps the SSCA of the one before.
+struct BatchPipe {
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t start = nullptr;                // the caller's stream at the start of a batch call
+  hipEvent_t sel[2] = {nullptr, nullptr};    // selection of the side stream's latest item ready
+  hipEvent_t done[2] = {nullptr, nullptr};   // SSCA of the side stream's latest item finished
+};
 struct DevState {
   std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables (read-only once built)
   std::map<hipStream_t, Scratch> streams;
+  BatchPipe pipe;
 };
+std::mutex g_batch_mu;  // one scd_ssca_batch call at a time: its side streams and events are per device
 // features (2 Np) + standardised features (2 Np) + activations (4 * 256) + logits (Np) + scores (Np) + conf
 constexpr int kSelStructFloats = (sizeof(scd::ChanSel) + 3) / 4 + 4;
 constexpr int kSelScratchFloats = 4 * 256 + 4 * 256 + 2 * 256 + 64 + kSelStructFloats;
@@ -856,9 +866,9 @@ namespace {
 // thresholds the scores, falls back below the confidence floor and writes the device-side selection. Leaves
 // the scores at *scores (device, Np floats), the confidence and fallback flag at *conf / *fell and the
 // ChanSel at *dsel, all in the library's selector scratch (checked arguments; takes the library lock itself).
-int learned_select(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector,
-                   unsigned char* mask, hipStream_t stream, float** scores, float** conf, int** fell,
-                   scd::ChanSel** dsel) {
+// The host-side checks of a learned call's arguments (no device access).
+int check_learned_args(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector,
+                       const unsigned char* mask) {
   if (!x || !win || !selector || !mask) return fail(SCD_ERR_NULL, "NULL argument");
   if (!selector->params || !selector->mu || !selector->sigma) return fail(SCD_ERR_MODEL, "selector has NULL arrays");
   if (reinterpret_cast<uintptr_t>(selector->params) % 16 != 0)
@@ -867,8 +877,15 @@ int learned_select(const float* x, int64_t N, int Np, const float* win, const sc
   if (!is_pow2(N) || N < (1 << 14) || N > (1 << 20))
     return fail(SCD_ERR_SIZE, "the learned form needs N a power of two in [2^14, 2^20]");
   if (!is_pow2(Np) || Np < 16 || Np > 256) return fail(SCD_ERR_SIZE, "Np must be a power of two in [16, 256]");
-  const scd::MlpLayout L = scd::mlp_layout(Np);
+  return SCD_OK;
+}
+
+int learned_select(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector,
+                   unsigned char* mask, hipStream_t stream, float** scores, float** conf, int** fell,
+                   scd::ChanSel** dsel) {
   int rc;
+  if ((rc = check_learned_args(x, N, Np, win, selector, mask))) return rc;
+  const scd::MlpLayout L = scd::mlp_layout(Np);
   float* f = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -959,12 +976,68 @@ int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts) {
   if (opts && opts->batch > 1) return fail(SCD_ERR_SIZE, "each item is one signal: opts->batch must be 0 or 1");
   if (opts && (opts->x_stride != 0 || opts->out_stride != 0))
     return fail(SCD_ERR_UNSUPPORTED, "strides do not apply to scd_ssca_batch items");
-  // Items share the stream, so the library's intermediate and selector scratch are reused in stream order.
+  if (n == 0) return SCD_OK;
+  std::lock_guard<std::mutex> blk(g_batch_mu);
+  hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
+  scd_opts so{};
+  if (opts) so = *opts;
+  so.batch = 1;
+  so.stream = stream;
+  // Items run in order on the caller's stream, which reuses its intermediate in stream order. The selector of
+  // a learned item runs on side stream i mod 2 into that stream's own scratch; the caller's stream waits for it
+  // before the item's SSCA, and the side stream waits for the SSCA of its previous item (the last reader of its
+  // selection) before it overwrites the scratch. The side streams are set up at the first learned item, once its
+  // arguments have been checked, and start after everything enqueued on the caller's stream before it.
+  BatchPipe* bp = nullptr;
+  auto setup = [&]() -> int {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev, rc;
+    if ((rc = current_device(&dev))) return rc;
+    BatchPipe& P = g_dev[dev].pipe;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < 2 && e == hipSuccess; ++j) {
+      if (!P.side[j]) e = hipStreamCreateWithFlags(&P.side[j], hipStreamNonBlocking);
+      if (e == hipSuccess && !P.sel[j]) e = hipEventCreateWithFlags(&P.sel[j], hipEventDisableTiming);
+      if (e == hipSuccess && !P.done[j]) e = hipEventCreateWithFlags(&P.done[j], hipEventDisableTiming);
+    }
+    if (e == hipSuccess && !P.start) e = hipEventCreateWithFlags(&P.start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(P.start, stream);
+    for (int j = 0; j < 2 && e == hipSuccess; ++j) e = hipStreamWaitEvent(P.side[j], P.start, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch side streams");
+    bp = &P;
+    return SCD_OK;
+  };
+  int nl = 0;  // learned items so far
   for (int i = 0; i < n; ++i) {
     const scd_ssca_item& it = items[i];
-    const int rc = it.selector
-                       ? scd_ssca_learned(it.x, it.N, it.Np, it.win, it.selector, it.out, it.mask, nullptr, opts)
-                       : scd_ssca_ex(it.x, it.N, it.Np, it.win, it.out, opts);
+    int rc;
+    if (!it.selector) {
+      rc = scd_ssca_ex(it.x, it.N, it.Np, it.win, it.out, &so);
+    } else {
+      rc = check_learned_args(it.x, it.N, it.Np, it.win, it.selector, it.mask);
+      if (rc == SCD_OK && so.precision != SCD_FP32 && so.precision != SCD_SPLIT_BF16)
+        rc = fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
+      if (rc == SCD_OK && !bp) rc = setup();
+    }
+    if (rc == SCD_OK && it.selector) {
+      const int j = nl++ & 1;
+      hipStream_t side = bp->side[j];
+      float *dsc, *dconf;
+      int* dfell;
+      scd::ChanSel* dsel;
+      hipError_t e = hipStreamWaitEvent(side, bp->done[j], 0);
+      if (e != hipSuccess) return hip_fail(e, "batch ordering");
+      rc = learned_select(it.x, it.N, it.Np, it.win, it.selector, it.mask, side, &dsc, &dconf, &dfell, &dsel);
+      if (rc == SCD_OK) {
+        e = hipEventRecord(bp->sel[j], side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, bp->sel[j], 0);
+        if (e != hipSuccess) return hip_fail(e, "batch ordering");
+        const scd::SelArg sel{dsel, it.Np / 16, it.Np / 32, it.Np};
+        rc = ssca_common(SscaPart::kWhole, it.x, it.N, it.Np, it.win, it.out, &so, &sel);
+        if (rc == SCD_OK && (e = hipEventRecord(bp->done[j], stream)) != hipSuccess)
+          return hip_fail(e, "batch ordering");
+      }
+    }
     if (rc != SCD_OK) {
       const std::string why = g_err;
       return fail(rc, "item %d: %s", i, why.c_str());
@@ -982,6 +1055,13 @@ void scd_shutdown(void) {
     (void)hipSetDevice(kv.first);
     (void)hipDeviceSynchronize();
     for (auto& p : kv.second.plans) (void)hipFree(p.second);
+    BatchPipe& P = kv.second.pipe;
+    for (int j = 0; j < 2; ++j) {
+      if (P.side[j]) (void)hipStreamDestroy(P.side[j]);
+      if (P.sel[j]) (void)hipEventDestroy(P.sel[j]);
+      if (P.done[j]) (void)hipEventDestroy(P.done[j]);
+    }
+    if (P.start) (void)hipEventDestroy(P.start);
     for (auto& sc : kv.second.streams) {
       if (sc.second.work) (void)hipFree(sc.second.work);
       if (sc.second.aux) (void)hipFree(sc.second.aux);

@@ -53,3 +53,30 @@ def test_ragged_batch_bad_item_is_named(dev):
     x = _x(sg.noise(4096, sg.rng_for(91, 0)), dev)
     with pytest.raises(scd.ScdError, match="item 1"):
         scd.ssca_batch([dict(x=x, Np=32), dict(x=x, Np=8192)])
+
+
+def test_learned_items_pipelined_equal_single_calls(dev):
+    """Five learned items (both side streams reused, Np 64 and 128) among plain ones, twice, on two streams:
+    each item's output and mask equal its single call's."""
+    sels = {Np: SEL.Selector.load(os.path.join(ROOT, "paper_2506_18003_amd", "models", f"selector_np{Np}.npz"), dev)
+            for Np in (64, 128)}
+    kinds = ["bpsk", "qpsk", "noise", "msk", "qam16", "am", "qpsk"]
+    items = []
+    for i, kind in enumerate(kinds):
+        N = 1 << (14 + (3 * i) % 5)
+        Np = 64 if i % 2 == 0 else 128
+        x = sg.generate(kind, N, sg.rng_for(92, i), 0.05 + 0.03 * i, 4 + i, 2.0 * i - 4.0)
+        items.append(dict(x=_x(x, dev), Np=Np, selector=None if i in (1, 4) else sels[Np]))
+    for prec, stream in (("fp32", torch.cuda.Stream(dev)), ("split_bf16", torch.cuda.Stream(dev))):
+        stream.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(stream):
+            got = scd.ssca_batch(items, precision=prec)
+            refs = [SEL.ssca_learned(it["x"], it["selector"], precision=prec)[:2] if it["selector"] is not None
+                    else (scd.ssca(it["x"], it["Np"], precision=prec), None) for it in items]
+        torch.cuda.synchronize()
+        for i, ((out, mask), (ref, rmask)) in enumerate(zip(got, refs)):
+            assert torch.equal(out, ref), (prec, i)
+            if rmask is None:
+                assert mask is None
+            else:
+                assert torch.equal(mask, rmask), (prec, i)
