@@ -376,17 +376,23 @@ typedef struct scd_ssca_item {
                                    unused                                                                  */
 } scd_ssca_item;
 
-/* SSCA of n signals of any lengths and channel counts, enqueued in item order on one stream (a library form
- * for mixed workloads; the paper estimates one signal at a time). An item without a selector runs as
- * scd_ssca_ex; an item with one runs as scd_ssca_learned with fell_back NULL, so the call never waits for the
- * GPU. The selectors of learned items run on two library-owned side streams (default priority) ordered by
- * events, so the selector of one item overlaps the SSCA of the one before; each item's outputs equal those of
- * its single call. The side streams start after the work already on opts' stream, and that stream waits for
- * them, so the results are ordered on it as for single calls. Batch calls on one process run one at a time on
- * the host. Every item uses opts' precision, stream and workspace. opts->batch must be 0 or 1 and both strides 0:
- * each item is one signal. A caller workspace must hold the largest item's intermediate; the library-owned one
- * grows to it, waiting for the device once when it grows. The call stops at the first item that fails and
- * returns that item's error code, with the item's index in scd_last_error; the items before it stay enqueued.
+/* SSCA of n signals of any lengths and channel counts (a library form for mixed workloads; the paper estimates
+ * one signal at a time). An item without a selector runs as scd_ssca_ex; an item with one runs as
+ * scd_ssca_learned with fell_back NULL, so the call never waits for the GPU. Each item's outputs equal those of
+ * its single call.
+ *   - Items run on four library-owned lanes (streams of default priority; item i on lane i mod 4), each with
+ *     its own scratch, so short items, whose grids cannot fill the GPU, and selectors overlap other items.
+ *     The lanes start after the work already on opts' stream, and that stream waits for all of them, so the
+ *     results are ordered on it as for single calls. With a caller workspace (one buffer) or a single item,
+ *     the items run in order on opts' stream instead.
+ *   - Every item uses opts' precision and workspace. opts->batch must be 0 or 1 and both strides 0: each item
+ *     is one signal. A caller workspace must hold the largest item's intermediate; the library's scratch grows
+ *     per lane to the largest item that lane runs, waiting for that lane once when it grows.
+ *   - Argument errors that the host can see in any item (sizes, NULL pointers, precision, selector fields)
+ *     are returned before anything is enqueued. A later failure (say a pointer that is not device memory)
+ *     stops the call at that item, and the items before it stay enqueued. Either way the error code is the
+ *     item's, with its index in scd_last_error.
+ *   - Batch calls in one process run one at a time on the host.
  * Errors: SCD_ERR_NULL (items NULL with n > 0), SCD_ERR_SIZE (n < 0 or opts->batch > 1), SCD_ERR_UNSUPPORTED
  * (nonzero strides), and those of scd_ssca_ex and scd_ssca_learned. */
 int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts);

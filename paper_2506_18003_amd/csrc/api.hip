@@ -34,13 +34,13 @@ struct Scratch {
   void* sel = nullptr;  // selector scratch: features, activations, scores, confidence, channel selection
   size_t sel_bytes = 0;
 };
-// Streams and events of the batch pipeline (scd_ssca_batch): the selectors of learned items run on two side
-// streams, each with its own scratch, so the selector of one item overlaps the SSCA of the one before.
+// Lanes of scd_ssca_batch: library-owned streams that each run whole items (selector, then SSCA) with their
+// own scratch, so short items, whose grids cannot fill the GPU, and selectors overlap other items.
+constexpr int kBatchLanes = 4;
 struct BatchPipe {
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t start = nullptr;                // the caller's stream at the start of a batch call
-  hipEvent_t sel[2] = {nullptr, nullptr};    // selection of the side stream's latest item ready
-  hipEvent_t done[2] = {nullptr, nullptr};   // SSCA of the side stream's latest item finished
+  hipStream_t lane[kBatchLanes] = {};
+  hipEvent_t start = nullptr;          // the caller's stream at the start of a batch call
+  hipEvent_t end[kBatchLanes] = {};    // each lane's last item of the call
 };
 struct DevState {
   std::map<std::pair<int64_t, int>, float2*> plans;  // (transform length, Np) -> tables (read-only once built)
@@ -880,6 +880,28 @@ int check_learned_args(const float* x, int64_t N, int Np, const float* win, cons
   return SCD_OK;
 }
 
+// The host-side checks of one scd_ssca_batch item (no device access), so that argument errors of any item are
+// found before the call enqueues anything.
+int check_batch_item(const scd_ssca_item& it, int precision) {
+  if (precision < SCD_FP32 || precision > SCD_FP16) return fail(SCD_ERR_SIZE, "unknown precision %d", precision);
+  if (it.selector) {
+    const int rc = check_learned_args(it.x, it.N, it.Np, it.win, it.selector, it.mask);
+    if (rc != SCD_OK) return rc;
+    if (!it.out) return fail(SCD_ERR_NULL, "NULL argument");
+    if (precision != SCD_FP32 && precision != SCD_SPLIT_BF16)
+      return fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
+    return SCD_OK;
+  }
+  if (!it.x || !it.win || !it.out) return fail(SCD_ERR_NULL, "input, window and output must be non-NULL");
+  if (!is_pow2(it.N) || it.N < 1024 || it.N > (1 << 20))
+    return fail(SCD_ERR_SIZE, "N = %lld must be a power of two in [2^10, 2^20]", static_cast<long long>(it.N));
+  if (!is_pow2(it.Np) || it.Np < 16 || it.Np > 256)
+    return fail(SCD_ERR_SIZE, "Np = %d must be a power of two in [16, 256]", it.Np);
+  if (precision != SCD_FP32 && it.Np > 128)
+    return fail(SCD_ERR_UNSUPPORTED, "16-bit channelizer precisions support Np <= 128 (got %d)", it.Np);
+  return SCD_OK;
+}
+
 int learned_select(const float* x, int64_t N, int Np, const float* win, const scd_selector* selector,
                    unsigned char* mask, hipStream_t stream, float** scores, float** conf, int** fell,
                    scd::ChanSel** dsel) {
@@ -976,73 +998,74 @@ int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts) {
   if (opts && opts->batch > 1) return fail(SCD_ERR_SIZE, "each item is one signal: opts->batch must be 0 or 1");
   if (opts && (opts->x_stride != 0 || opts->out_stride != 0))
     return fail(SCD_ERR_UNSUPPORTED, "strides do not apply to scd_ssca_batch items");
+  const int prec = opts ? opts->precision : SCD_FP32;
+  for (int i = 0; i < n; ++i) {
+    const int rc = check_batch_item(items[i], prec);
+    if (rc != SCD_OK) {
+      const std::string why = g_err;
+      return fail(rc, "item %d: %s", i, why.c_str());
+    }
+  }
   if (n == 0) return SCD_OK;
   std::lock_guard<std::mutex> blk(g_batch_mu);
   hipStream_t stream = (opts && opts->stream) ? static_cast<hipStream_t>(opts->stream) : g_stream;
   scd_opts so{};
   if (opts) so = *opts;
   so.batch = 1;
-  so.stream = stream;
-  // Items run in order on the caller's stream, which reuses its intermediate in stream order. The selector of
-  // a learned item runs on side stream i mod 2 into that stream's own scratch; the caller's stream waits for it
-  // before the item's SSCA, and the side stream waits for the SSCA of its previous item (the last reader of its
-  // selection) before it overwrites the scratch. The side streams are set up at the first learned item, once its
-  // arguments have been checked, and start after everything enqueued on the caller's stream before it.
+  // Item i runs on lane i mod kBatchLanes: its selector (if any) and its SSCA in that lane's order, on the lane's
+  // own scratch. The lanes start after the work already on the caller's stream, and the caller's stream waits
+  // for all of them at the end. A caller workspace is one buffer, so with one the items run in order on the
+  // caller's stream, as does a single item.
+  const int K = (n > 1 && !(opts && opts->workspace)) ? kBatchLanes : 1;
+  hipStream_t lanes[kBatchLanes] = {stream, stream, stream, stream};
   BatchPipe* bp = nullptr;
-  auto setup = [&]() -> int {
+  if (K > 1) {
     std::lock_guard<std::mutex> lk(g_mu);
     int dev, rc;
     if ((rc = current_device(&dev))) return rc;
     BatchPipe& P = g_dev[dev].pipe;
     hipError_t e = hipSuccess;
-    for (int j = 0; j < 2 && e == hipSuccess; ++j) {
-      if (!P.side[j]) e = hipStreamCreateWithFlags(&P.side[j], hipStreamNonBlocking);
-      if (e == hipSuccess && !P.sel[j]) e = hipEventCreateWithFlags(&P.sel[j], hipEventDisableTiming);
-      if (e == hipSuccess && !P.done[j]) e = hipEventCreateWithFlags(&P.done[j], hipEventDisableTiming);
+    for (int j = 0; j < K && e == hipSuccess; ++j) {
+      if (!P.lane[j]) e = hipStreamCreateWithFlags(&P.lane[j], hipStreamNonBlocking);
+      if (e == hipSuccess && !P.end[j]) e = hipEventCreateWithFlags(&P.end[j], hipEventDisableTiming);
     }
     if (e == hipSuccess && !P.start) e = hipEventCreateWithFlags(&P.start, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(P.start, stream);
-    for (int j = 0; j < 2 && e == hipSuccess; ++j) e = hipStreamWaitEvent(P.side[j], P.start, 0);
-    if (e != hipSuccess) return hip_fail(e, "batch side streams");
+    for (int j = 0; j < K && e == hipSuccess; ++j) e = hipStreamWaitEvent(P.lane[j], P.start, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch lanes");
+    for (int j = 0; j < K; ++j) lanes[j] = P.lane[j];
     bp = &P;
-    return SCD_OK;
-  };
-  int nl = 0;  // learned items so far
-  for (int i = 0; i < n; ++i) {
+  }
+  int rc = SCD_OK, bad = -1;
+  for (int i = 0; i < n && rc == SCD_OK; ++i) {
     const scd_ssca_item& it = items[i];
-    int rc;
+    so.stream = lanes[i % K];
     if (!it.selector) {
       rc = scd_ssca_ex(it.x, it.N, it.Np, it.win, it.out, &so);
     } else {
-      rc = check_learned_args(it.x, it.N, it.Np, it.win, it.selector, it.mask);
-      if (rc == SCD_OK && so.precision != SCD_FP32 && so.precision != SCD_SPLIT_BF16)
-        rc = fail(SCD_ERR_UNSUPPORTED, "the learned form runs in FP32 or split-BF16");
-      if (rc == SCD_OK && !bp) rc = setup();
-    }
-    if (rc == SCD_OK && it.selector) {
-      const int j = nl++ & 1;
-      hipStream_t side = bp->side[j];
       float *dsc, *dconf;
       int* dfell;
       scd::ChanSel* dsel;
-      hipError_t e = hipStreamWaitEvent(side, bp->done[j], 0);
-      if (e != hipSuccess) return hip_fail(e, "batch ordering");
-      rc = learned_select(it.x, it.N, it.Np, it.win, it.selector, it.mask, side, &dsc, &dconf, &dfell, &dsel);
+      rc = learned_select(it.x, it.N, it.Np, it.win, it.selector, it.mask, lanes[i % K], &dsc, &dconf, &dfell,
+                          &dsel);
       if (rc == SCD_OK) {
-        e = hipEventRecord(bp->sel[j], side);
-        if (e == hipSuccess) e = hipStreamWaitEvent(stream, bp->sel[j], 0);
-        if (e != hipSuccess) return hip_fail(e, "batch ordering");
         const scd::SelArg sel{dsel, it.Np / 16, it.Np / 32, it.Np};
         rc = ssca_common(SscaPart::kWhole, it.x, it.N, it.Np, it.win, it.out, &so, &sel);
-        if (rc == SCD_OK && (e = hipEventRecord(bp->done[j], stream)) != hipSuccess)
-          return hip_fail(e, "batch ordering");
       }
     }
-    if (rc != SCD_OK) {
-      const std::string why = g_err;
-      return fail(rc, "item %d: %s", i, why.c_str());
-    }
+    if (rc != SCD_OK) bad = i;
   }
+  const std::string why = g_err;
+  // The caller's stream waits for every lane, also after a failing item (the items before it stay enqueued).
+  if (bp) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < K && e == hipSuccess; ++j) {
+      e = hipEventRecord(bp->end[j], bp->lane[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, bp->end[j], 0);
+    }
+    if (e != hipSuccess && rc == SCD_OK) return hip_fail(e, "batch lanes");
+  }
+  if (rc != SCD_OK) return fail(rc, "item %d: %s", bad, why.c_str());
   return SCD_OK;
 }
 
@@ -1056,10 +1079,9 @@ void scd_shutdown(void) {
     (void)hipDeviceSynchronize();
     for (auto& p : kv.second.plans) (void)hipFree(p.second);
     BatchPipe& P = kv.second.pipe;
-    for (int j = 0; j < 2; ++j) {
-      if (P.side[j]) (void)hipStreamDestroy(P.side[j]);
-      if (P.sel[j]) (void)hipEventDestroy(P.sel[j]);
-      if (P.done[j]) (void)hipEventDestroy(P.done[j]);
+    for (int j = 0; j < kBatchLanes; ++j) {
+      if (P.lane[j]) (void)hipStreamDestroy(P.lane[j]);
+      if (P.end[j]) (void)hipEventDestroy(P.end[j]);
     }
     if (P.start) (void)hipEventDestroy(P.start);
     for (auto& sc : kv.second.streams) {

@@ -55,9 +55,10 @@ def test_ragged_batch_bad_item_is_named(dev):
         scd.ssca_batch([dict(x=x, Np=32), dict(x=x, Np=8192)])
 
 
-def test_learned_items_pipelined_equal_single_calls(dev):
-    """Five learned items (both side streams reused, Np 64 and 128) among plain ones, twice, on two streams:
-    each item's output and mask equal its single call's."""
+def test_batch_lanes_equal_single_calls(dev):
+    """Seven items, five of them learned (Np 64 and 128), on the four lanes in FP32 and split-BF16 and in order
+    through a caller workspace, each time on a stream of its own: each item's output and mask equal its single
+    call's."""
     sels = {Np: SEL.Selector.load(os.path.join(ROOT, "paper_2506_18003_amd", "models", f"selector_np{Np}.npz"), dev)
             for Np in (64, 128)}
     kinds = ["bpsk", "qpsk", "noise", "msk", "qam16", "am", "qpsk"]
@@ -67,10 +68,12 @@ def test_learned_items_pipelined_equal_single_calls(dev):
         Np = 64 if i % 2 == 0 else 128
         x = sg.generate(kind, N, sg.rng_for(92, i), 0.05 + 0.03 * i, 4 + i, 2.0 * i - 4.0)
         items.append(dict(x=_x(x, dev), Np=Np, selector=None if i in (1, 4) else sels[Np]))
-    for prec, stream in (("fp32", torch.cuda.Stream(dev)), ("split_bf16", torch.cuda.Stream(dev))):
+    ws = torch.empty(max(it["Np"] * it["x"].shape[0] for it in items), dtype=torch.complex64, device=dev)
+    for prec, stream, wsp in (("fp32", torch.cuda.Stream(dev), None), ("split_bf16", torch.cuda.Stream(dev), None),
+                              ("fp32", torch.cuda.Stream(dev), ws)):
         stream.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(stream):
-            got = scd.ssca_batch(items, precision=prec)
+            got = scd.ssca_batch(items, precision=prec, workspace=wsp)
             refs = [SEL.ssca_learned(it["x"], it["selector"], precision=prec)[:2] if it["selector"] is not None
                     else (scd.ssca(it["x"], it["Np"], precision=prec), None) for it in items]
         torch.cuda.synchronize()
