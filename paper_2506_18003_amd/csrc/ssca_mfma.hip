@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
   const int cg = SEL ? sel->pair[u] : u;
   x += blockIdx.y * xbs;
   xhi += blockIdx.y * pbs;
-  xlo += blockIdx.y * pbs;
+  (void)xlo;  // the paired form reads the interleaved plane (hi and lo words) through xhi
   T += blockIdx.y * tbs;
   const auto trs = make_rsrc_u(T, static_cast<unsigned>(NP) * 8u * static_cast<unsigned>(N));  // one signal's T
   const float2* rlo = tabs + kTabRotLo;
