@@ -1017,7 +1017,8 @@ int scd_ssca_batch(const scd_ssca_item* items, int n, const scd_opts* opts) {
   // for all of them at the end. A caller workspace is one buffer, so with one the items run in order on the
   // caller's stream, as does a single item.
   const int K = (n > 1 && !(opts && opts->workspace)) ? kBatchLanes : 1;
-  hipStream_t lanes[kBatchLanes] = {stream, stream, stream, stream};
+  hipStream_t lanes[kBatchLanes];
+  for (hipStream_t& l : lanes) l = stream;
   BatchPipe* bp = nullptr;
   if (K > 1) {
     std::lock_guard<std::mutex> lk(g_mu);
