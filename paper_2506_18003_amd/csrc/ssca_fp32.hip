@@ -410,9 +410,13 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
   if constexpr (NP >= 32) {
     const int64_t single_blocks = static_cast<int64_t>(M2) * sel.nsub * batch;
     const int64_t pair_blocks = static_cast<int64_t>(M2) * sel.npair * batch;
-    // A pair computes both its subsets, so a selection that leaves pairs half used runs single subsets.
+    // A pair computes both its subsets, so a selection that leaves pairs half used runs single subsets. At
+    // Np >= 128 a lane folds Np/16 >= 8 taps, and the pair's shared fold wins at every grid measured (N = 2^18 to
+    // 2^20: 10-20% faster at Np = 128, 27-30% at Np = 256); at Np = 64 two single-subset workgroups per CU win
+    // once their grid fills the GPU for several rounds.
     const bool pairs_full = sel.nsub >= 2 * sel.npair;
-    if (pairs_full && single_blocks < kSingleMinBlocks && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
+    const bool pairs_pay = NP >= 128 || single_blocks < kSingleMinBlocks;
+    if (pairs_full && pairs_pay && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
     else launch(std::false_type{});
   } else {
     launch(std::false_type{});

@@ -120,6 +120,22 @@ def test_ssca_cfg3_full_size_sampled_strips(dev):
         assert np.abs(g - refs[k]).max() / peak <= TOL_FP32, k
 
 
+@pytest.mark.parametrize("N,Np,strips", [
+    (1 << 20, 128, (0, 3, 8, 67, 100, 127)),       # paired Stage 1 at Np = 128 (both subsets of a pair)
+    (1 << 18, 256, (0, 5, 21, 130, 200, 255)),     # paired Stage 1 at Np = 256, 16 taps per lane
+])
+def test_ssca_large_np_sampled_strips(dev, N, Np, strips):
+    """The paired Stage 1 at Np = 128 and 256 on grids that fill the GPU; strips compared in full."""
+    x = sg.qpsk(N, 0.1, 8, 5.0, sg.rng_for(53, Np))
+    w = w32(Np)
+    S = scd.ssca(to_gpu(x, dev), Np, win=torch.from_numpy(w).to(dev))
+    xf = f64(x)
+    refs = {k: O.ssca_strip(xf, Np, w.astype(np.float64), k) for k in strips}
+    peak = max(np.abs(r).max() for r in refs.values())
+    for k in strips:
+        assert np.abs(S[k].cpu().numpy() - refs[k]).max() / peak <= TOL_FP32, k
+
+
 def test_stages_equal_whole(dev):
     N, Np = 1 << 16, 64
     x = to_gpu(sg.qpsk(N, 0.1, 8, 5.0, sg.rng_for(52, 0)), dev)
