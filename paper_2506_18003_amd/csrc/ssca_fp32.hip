@@ -33,7 +33,7 @@ constexpr int kHalfSeqs = 32;         // 8 channels x 4 residues per LDS exchang
 constexpr int kXchgFloats = kHalfSeqs * kSeqStride;
 constexpr int kP2Threads = 256;
 constexpr int kPairMinBlocks = 256;   // paired Stage-1 grids at least this large (one block per CU)
-constexpr int kSingleMinBlocks = 2048;  // single-subset grids this large fill two blocks per CU for four rounds
+constexpr int kSingleMinBlocks = 4096;  // single-subset grids this large fill two blocks per CU for eight rounds
 
 // omega_N^a for 0 <= a < N from the two-level table: omega_N^{a mod 1024} * omega_1024^{(a / 1024) * 1024 / M2}.
 __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
@@ -412,8 +412,9 @@ hipError_t pass1(const float2* x, int N, int M2, int m2shift, const float* win, 
     const int64_t pair_blocks = static_cast<int64_t>(M2) * sel.npair * batch;
     // A pair computes both its subsets, so a selection that leaves pairs half used runs single subsets. At
     // Np >= 128 a lane folds Np/16 >= 8 taps, and the pair's shared fold wins at every grid measured (N = 2^18 to
-    // 2^20: 10-20% faster at Np = 128, 27-30% at Np = 256); at Np = 64 two single-subset workgroups per CU win
-    // once their grid fills the GPU for several rounds.
+    // 2^20: 10-20% faster at Np = 128, 27-30% at Np = 256). At Np = 32 and 64 pairs won by 7-14% on grids of up
+    // to 2048 single-subset blocks (Np = 32 at N = 2^18..2^20, Np = 64 at 2^17..2^19); at 4096 (Np = 64,
+    // N = 2^20) the two measured equal or single subsets faster.
     const bool pairs_full = sel.nsub >= 2 * sel.npair;
     const bool pairs_pay = NP >= 128 || single_blocks < kSingleMinBlocks;
     if (pairs_full && pairs_pay && pair_blocks >= kPairMinBlocks) launch(std::true_type{});
