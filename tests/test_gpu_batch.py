@@ -83,3 +83,21 @@ def test_batch_lanes_equal_single_calls(dev):
                 assert mask is None
             else:
                 assert torch.equal(mask, rmask), (prec, i)
+
+
+def test_batch_error_mid_way_keeps_earlier_items(dev):
+    """Item 2's output is host memory, which the library rejects (SCD_ERR_PTR) before any of its work is
+    enqueued: the call names item 2, and items 0 and 1, already enqueued on lanes, finish correctly."""
+    sel = SEL.Selector.load(os.path.join(ROOT, "paper_2506_18003_amd", "models", "selector_np64.npz"), dev)
+    xs = [_x(sg.qpsk(1 << 15, 0.1, 8, 4.0, sg.rng_for(93, i)), dev) for i in range(3)]
+    items = [dict(x=xs[0], Np=64), dict(x=xs[1], Np=64, selector=sel),
+             dict(x=xs[2], Np=64, out=torch.empty(64, 1 << 15, dtype=torch.complex64))]
+    outs = [torch.empty(64, 1 << 15, dtype=torch.complex64, device=dev),
+            torch.zeros(64, 1 << 15, dtype=torch.complex64, device=dev)]
+    items[0]["out"], items[1]["out"] = outs
+    with pytest.raises(scd.ScdError, match="item 2"):
+        scd.ssca_batch(items)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], scd.ssca(xs[0], 64))
+    ref, _, _ = SEL.ssca_learned(xs[1], sel)
+    assert torch.equal(outs[1], ref)
