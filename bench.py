@@ -200,8 +200,9 @@ def main():
                     help="also run one 256 MiB read + 256 MiB write elementwise kernel (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the SSCA strips would shard over GPUs by channel, but this "
-              "build runs and reports a single MI355X (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the SSCA strips would shard over GPUs by channel (scd_ssca_strips "
+              "computes one GPU's share, and the `shard` line times it), but this build runs and reports a single "
+              "MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
