@@ -143,3 +143,15 @@ def test_strips_batch_through_a_small_workspace(dev):
     out = scd.ssca_strips(x, Np, ks, out=sentinel.clone(), workspace=ws)
     torch.cuda.synchronize()
     _check_rows(out, full, sentinel, ks)
+
+
+def test_strips_batch_at_n1024(dev):
+    """N = 1024 (Stage 1 alone is the transform): each signal's listed rows come from the library's scratch."""
+    N, Np = 1024, 64
+    ks = [0, 17, 40, 63]
+    x = _x(N, 7, dev, batch=3)
+    full = scd.ssca(x, Np)
+    sentinel = torch.full((3, Np, N), complex(4.0, 4.0), dtype=torch.complex64, device=dev)
+    out = scd.ssca_strips(x, Np, ks, out=sentinel.clone())
+    torch.cuda.synchronize()
+    _check_rows(out, full, sentinel, ks)
