@@ -207,9 +207,18 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
   float2* xb = buf + half * kXchgFloats;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xb[(kk * 4 + r) * kSeqStride + t + (t >> 4)] = col[r][8 * h + kk];
+    }
+    __syncthreads();
     if constexpr (SEL && !PAIR) {
-      // Stage 2 reads only selected strips: a half whose eight strips k = c + S (8 h + kk) are all unselected is
-      // skipped by the whole workgroup (c is uniform).
+      // Stage 2 reads only selected strips: a half whose eight strips k = c + S (8 h + kk) are all unselected
+      // skips its DFTs and stores (the whole workgroup: c is uniform). The test comes after the exchange writes,
+      // so the half's channel values leave the registers on both paths; skipping the writes as well made this
+      // kernel spill.
       unsigned any = 0;
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
@@ -218,13 +227,6 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       }
       if (!(any & 1u)) continue;
     }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xb[(kk * 4 + r) * kSeqStride + t + (t >> 4)] = col[r][8 * h + kk];
-    }
-    __syncthreads();
     // Last radix-16 stage output m = j + 16 i of sequence b = 4 kk + r is m1' = (r + 4 j) + 64 i, stored at
     // T[k][m1' / 16][m2][m1' % 16] = T[k][j / 4 + 4 i][m2][4 (j % 4) + r]: a per-butterfly lane offset plus
     // i * 4 M2 * 16 elements, the latter a scalar offset of the buffer store.
