@@ -57,8 +57,8 @@ __device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw
 // subset c (strips c mod Np/32) is the 32-point DFT of u[j0 + 16 e] = sum_m hc[j0 + 32 m + 16 e] x[...]; its
 // even outputs are the 16-point DFT of u[j0] + u[j0 + 16] (subset c) and its odd outputs that of
 // (u[j0] - u[j0 + 16]) omega_32^{j0} (subset c + Np/32). Each thread then takes the 16-point DFT and
-// multiplies by conj(x[n]) (and, when Np does not divide M2, by the per-frame down-conversion factor),
-// keeping the 16 channel values in registers.
+// multiplies by conj(x[n]) and the down-conversion's constant part (the k'-dependent part is the column shift
+// of the fold's LDS row), keeping the 16 channel values in registers.
 //
 // The M1 = 1024-point DFT over m1 = t + 256 f is a 4-point DFT over f in registers, a twiddle
 // omega_1024^{t r}, and a 256-point DFT over t in LDS (two halves of 8 channels), giving m1' = r + 4 s. Its
@@ -122,10 +122,12 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
     hl[j1] = cscale(tabs[kTabRoots + ((cg * j) & (NP - 1))], win[j]);
   }
   const float2 w32 = tw_g[32 * j0];  // omega_32^{j0}
-  // When Np divides M2 the down-conversion factor omega_Np^{(c + S k') m2} does not depend on the frame. Its
-  // k'-dependent part omega_16^{k' m2} is a cyclic shift of the 16-point DFT's input by m2, applied by storing
-  // residue j0 at column (j0 + m2) mod 16; the constant part omega_Np^{c m2} goes into conj(x[n]).
-  const int jcol = PHASE_BY_M2 ? ((j0 + m2) & 15) : j0;
+  // The down-conversion factor of frame n splits as omega_Np^{(c + S k') n} = omega_Np^{c n} omega_16^{k' n}. Its
+  // k'-dependent part is a cyclic shift of the 16-point DFT's input by n, applied by storing residue j0 at column
+  // (j0 + n) mod 16; the constant part omega_Np^{c n} goes into conj(x[n]). When Np divides M2, n = m2 (mod Np)
+  // for every frame, so both are fixed for the workgroup; otherwise the column follows each round's frame and
+  // the constant each thread's frame.
+  const int jcol = PHASE_BY_M2 ? ((j0 + m2) & 15) : (j0 + fi * M2 + m2);
   const float2 cphase = PHASE_BY_M2 ? tabs[kTabRoots + ((c * m2) & (NP - 1))] : make_float2(1.f, 0.f);
   // Round g folds frames m1 = FPR g + fi; its NT samples sit at x[base + 16 j1].
   const int base0 = xoff + fi * M2 + m2 - D + j0;
@@ -144,7 +146,8 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
 #pragma unroll
     for (int r = 0; r < RPG; ++r) {
       const int g = RPG * f + r;
-      const int row = (FPR * r + fi) * kURow + jcol;
+      // the column of frame m1 = 256 f + FPR r + fi, n = m1 M2 + m2
+      const int row = (FPR * r + fi) * kURow + (PHASE_BY_M2 ? jcol : ((jcol + (256 * f + FPR * r) * M2) & 15));
       // Tap j = D of frame m1 is the frame's own sample x[n] (n - D + j = n): the lane of residue D mod 16
       // holds it as tap D / 16 and parks it in the row's padding slot for the channel-data product.
       if (YM == 0 && j0 == (D & 15)) ub[(FPR * r + fi) * kURow + 16] = ring[g % PF][D >> 4];
@@ -180,16 +183,10 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
       xn = load_c64(make_rsrc(y + blockIdx.y * xbs, N * 8), n);
       if constexpr (YM == 2) xn = cconj(xn);
     }
-    const float2 xp = cmulc(xn, cphase);  // x[n] conj(omega_Np^{c m2})
+    // x[n] conj(omega_Np^{c n})
+    const float2 xp = cmulc(xn, PHASE_BY_M2 ? cphase : rt[(c * n) & (NP - 1)]);
 #pragma unroll
-    for (int kp = 0; kp < 16; ++kp) {
-      if constexpr (PHASE_BY_M2) {
-        col[f][kp] = cmulc(u[kp], xp);
-      } else {
-        const int k = c + S * kp;
-        col[f][kp] = cmul(u[kp], cmulc(rt[(k * n) & (NP - 1)], xn));
-      }
-    }
+    for (int kp = 0; kp < 16; ++kp) col[f][kp] = cmulc(u[kp], xp);
   }
 
   // 4-point DFT over f and twiddle omega_1024^{t r}: col[r][k'] now holds residue r of channel k'.

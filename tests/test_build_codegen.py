@@ -4,8 +4,8 @@
   offset (plus, at most, an immediate offset, which the buffer range check includes: the checked offset is the
   32-bit sum of both); a split or narrowed load would read past the signal instead of the zero padding, and a
   scalar offset would escape the check.
-* The headline Stage-1 kernel (Np = 64, Np dividing M2, all strips), its form with a device-side selection (the
-  learned path and strip lists) and the Stage-2 kernels do not spill registers.
+* No Stage-1 form (the headline kernel, its selection form, subset pairs, the per-frame down-conversion of
+  short signals, the cross forms, every Np) and no Stage-2 kernel spills registers.
 """
 import os
 import re
@@ -55,12 +55,11 @@ def _spills(asm):
 
 def test_hot_kernels_do_not_spill(asm):
     sp = _spills(asm)
-    # Stage 1 at Np = 64 with Np dividing M2, single subsets: every strip, and with a device-side selection (the
-    # learned form and strip lists)
-    hot = [n for n in sp if "ssca_pass1_fp32ILi64ELb1ELb0ELb0E" in n or "ssca_pass1_fp32ILi64ELb1ELb1ELb0E" in n
-           or "ssca_pass2_fp32" in n]
-    assert any("pass1_fp32ILi64ELb1ELb0ELb0E" in n for n in hot)
-    assert any("pass1_fp32ILi64ELb1ELb1ELb0E" in n for n in hot)
+    # every Stage-1 form (each Np, both down-conversion forms, selection, subset pairs, cross forms) and Stage 2
+    hot = [n for n in sp if "ssca_pass1_fp32" in n or "ssca_pass2_fp32" in n]
+    assert any("pass1_fp32ILi64ELb1ELb0ELb0E" in n for n in hot)  # the headline kernel
+    assert any("pass1_fp32ILi64ELb1ELb1ELb0E" in n for n in hot)  # the same with a device-side selection
+    assert any("pass1_fp32ILi64ELb0E" in n for n in hot)          # per-frame down-conversion (Np does not divide M2)
     assert any("pass2" in n for n in hot)
     for n in hot:
         assert sp[n] == 0, n
