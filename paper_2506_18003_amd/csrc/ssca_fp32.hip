@@ -248,19 +248,20 @@ __global__ __launch_bounds__(PAIR ? 2 * kP1Threads : kP1Threads, PAIR ? 1 : 2) v
 // m2, and one 128-byte run of the output per m2'. Each thread works on pairs of adjacent rows, so every global
 // and LDS access moves 16 bytes; element (row b, m) sits at LDS m*16 + b. The stage structure is the
 // Stockham one of lds_fft, applied to row pairs: the first stage streams straight from HBM and the last
-// stage streams straight to HBM (nontemporal: each byte is touched once).
-template <int L, int NS>
+// stage streams straight to HBM (nontemporal: each byte is touched once). NT threads share the 16 rows; tw
+// holds omega_TWN^e for e < TWN.
+template <int L, int NS, int NT, int TWN>
 __device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2* __restrict__ dst, float2* buf,
                                          const float2* tw, int tid) {
   constexpr int R = StageRadix<L, NS>::value;
   constexpr int NBF = 8 * (L / R);  // (row pair, butterfly) work items
-  constexpr int PER = (NBF + kP2Threads - 1) / kP2Threads;
+  constexpr int PER = (NBF + NT - 1) / NT;
   constexpr bool FIRST = NS == 1, LAST = NS * R == L;
   float2 a[PER][R], b[PER][R];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int bf = tid + p * kP2Threads;
-    if (NBF % kP2Threads == 0 || bf < NBF) {
+    const int bf = tid + p * NT;
+    if (NBF % NT == 0 || bf < NBF) {
       const int rp = bf & 7, j = bf >> 3, k = j % NS;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
@@ -276,7 +277,7 @@ __device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2*
       if constexpr (NS > 1) {
 #pragma unroll
         for (int i = 1; i < R; ++i) {
-          const float2 w = tw[(i * k * (1024 / (NS * R))) & 1023];
+          const float2 w = tw[(i * k * (TWN / (NS * R))) & (TWN - 1)];
           a[p][i] = cmul(a[p][i], w);
           b[p][i] = cmul(b[p][i], w);
         }
@@ -288,8 +289,8 @@ __device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2*
   if constexpr (!FIRST) __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int bf = tid + p * kP2Threads;
-    if (NBF % kP2Threads == 0 || bf < NBF) {
+    const int bf = tid + p * NT;
+    if (NBF % NT == 0 || bf < NBF) {
       const int rp = bf & 7, j = bf >> 3, k = j % NS;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
@@ -300,25 +301,37 @@ __device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2*
     }
   }
   if constexpr (!LAST) __syncthreads();
-  if constexpr (!LAST) p2_stage<L, NS * R>(src, dst, buf, tw, tid);
+  if constexpr (!LAST) p2_stage<L, NS * R, NT, TWN>(src, dst, buf, tw, tid);
 }
+
+// Short strips (M2 <= 64) hold only 16 M2 points per 16 rows: one wave takes each block of 16 m1', a workgroup
+// takes four such blocks of one channel, and LDS holds only the M2 twiddles they use. Longer strips give each
+// block the whole workgroup and the 1024-entry table.
+template <int M2>
+struct P2Shape {
+  static constexpr int NT = M2 >= 128 ? kP2Threads : 64;  // threads per block of 16 m1'
+  static constexpr int G = kP2Threads / NT;                // blocks per workgroup
+  static constexpr int TWN = M2 >= 128 ? 1024 : M2;        // twiddle entries: omega_TWN^e
+};
 
 template <int M2>
 __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __restrict__ T,
                                                              const float2* __restrict__ tabs,
                                                              float2* __restrict__ out, int N, int64_t tbs,
                                                              int64_t obs, const ChanSel* __restrict__ sel) {
-  __shared__ float2 buf[M2 * 16];
-  __shared__ float2 tw[1024];
+  using Sh = P2Shape<M2>;
+  __shared__ float2 buf[Sh::G * M2 * 16];
+  __shared__ float2 tw[Sh::TWN];
   const int tid = threadIdx.x;
-  const int mb = blockIdx.x;  // block of 16 consecutive m1'
+  const int g = tid / Sh::NT;
+  const int mb = blockIdx.x * Sh::G + g;  // block of 16 consecutive m1'
   if (sel && static_cast<int>(blockIdx.y) >= sel->nch) return;
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
-  for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];
+  for (int i = tid; i < Sh::TWN; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i * (1024 / Sh::TWN)];
   __syncthreads();
   const float2* src = T + blockIdx.z * tbs + (static_cast<int64_t>(k) * (kM1 / 16) + mb) * (M2 * 16);
   float2* dst = out + blockIdx.z * obs + static_cast<int64_t>(k) * N + mb * 16;
-  p2_stage<M2, 1>(src, dst, buf, tw, tid);
+  p2_stage<M2, 1, Sh::NT, Sh::TWN>(src, dst, buf + g * (M2 * 16), tw, tid % Sh::NT);
 }
 
 // Stage 2 for M2 = 1024 as 32 x 32, with m2 = j + 32 i and m2' = i' + 32 j':
@@ -428,11 +441,13 @@ template <int M2>
 hipError_t pass2(const float2* T, const float2* tabs, float2* out, int N, int batch, int64_t tbs, int64_t obs,
                  const SelArg& sel, hipStream_t s) {
   if (sel.nch <= 0) return hipSuccess;
-  dim3 grid(kM1 / 16, sel.nch, batch);
-  if constexpr (M2 == 1024)
+  if constexpr (M2 == 1024) {
+    dim3 grid(kM1 / 16, sel.nch, batch);
     hipLaunchKernelGGL(ssca_pass2_fp32_32x32, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
-  else
+  } else {
+    dim3 grid(kM1 / 16 / P2Shape<M2>::G, sel.nch, batch);
     hipLaunchKernelGGL(ssca_pass2_fp32<M2>, grid, dim3(kP2Threads), 0, s, T, tabs, out, N, tbs, obs, sel.dev);
+  }
   return hipGetLastError();
 }
 
