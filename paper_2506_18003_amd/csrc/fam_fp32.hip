@@ -41,16 +41,24 @@ __global__ __launch_bounds__(kChanThreads) void fam_chan_fp32(const float2* __re
   const int len = P * L;
   x += blockIdx.y * xbs;
   xt += blockIdx.y * xtbs;
-  for (int i = tid; i < 1024; i += kChanThreads) tw[i] = tabs[kTabTw1024 + i];
-  for (int i = tid; i < NP; i += kChanThreads) rt[i] = tabs[kTabRoots + i];
-  for (int e = tid; e < F * NP; e += kChanThreads) {
+  lds_copy<1024, kChanThreads>(tw, tabs + kTabTw1024, tid);
+  lds_copy<NP, kChanThreads>(rt, tabs + kTabRoots, tid);
+  // Samples outside [0, P L), and every sample of the frames p >= P, read as zero through a range-checked
+  // buffer load, so all of a thread's loads are in flight before its first LDS write.
+  constexpr int PER = F * NP / kChanThreads;
+  const auto xr = make_rsrc(x, len * 8);
+  float2 xv[PER];
+  float wv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int e = tid + r * kChanThreads;
     const int f = e / NP, j = e % NP;
     const int p = p0 + f;
-    const int idx = p * L - D + j;
-    float2 v = make_float2(0.f, 0.f);
-    if (p < P && static_cast<unsigned>(idx) < static_cast<unsigned>(len)) v = cscale(x[idx], win[j]);
-    buf[e] = v;
+    xv[r] = load_c64(xr, p < P ? p * L - D + j : -1);
+    wv[r] = win[j];
   }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) buf[tid + r * kChanThreads] = cscale(xv[r], wv[r]);
   __syncthreads();
   auto st = [&](int f, int k, float2 v) {
     const int p = p0 + f;
@@ -87,8 +95,8 @@ __global__ __launch_bounds__(kPairThreads) void fam_pair_fp32(const float2* __re
   const int k = blockIdx.y;
   xt += blockIdx.z * xtbs;
   yt += blockIdx.z * xtbs;
-  for (int i = tid; i < TWN; i += kPairThreads) tw[i] = tabs[kTabTw1024 + i * (1024 / TWN)];
-  for (int i = tid; i < P; i += kPairThreads) rk[i] = xt[static_cast<int64_t>(k) * P + i];
+  lds_copy<TWN, kPairThreads, 1024 / TWN>(tw, tabs + kTabTw1024, tid);
+  lds_copy<P, kPairThreads>(rk, xt + static_cast<int64_t>(k) * P, tid);
   __syncthreads();
   const float2* rl = yt + static_cast<int64_t>(l0) * P;
   auto ld = [&](int b, int m) { return CONJ ? cmul(rk[m], rl[b * P + m]) : cmulc(rk[m], rl[b * P + m]); };

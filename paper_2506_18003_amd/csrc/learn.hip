@@ -82,11 +82,19 @@ __global__ __launch_bounds__(kSegThreads) void seg_periodogram_kernel(const floa
   const int h = blockIdx.x & 1, c = blockIdx.x >> 1, b = blockIdx.y, sig = blockIdx.z;
   const int tid = threadIdx.x;
   const float2* seg = x + sig * xs + static_cast<int64_t>(b) * (N / kBF);
-  for (int i = tid; i < XL + 1; i += kSegThreads) {
-    const int n = i - D;
-    xl[i] = (n >= 0 && n < kNC) ? seg[n] : make_float2(0.f, 0.f);
+  {
+    // Samples outside the segment read as zero through a range-checked buffer load; every load of a thread is
+    // issued before its first LDS write.
+    constexpr int PER = (XL + 1 + kSegThreads - 1) / kSegThreads;
+    const auto sr = make_rsrc(seg, kNC * 8);
+    float2 v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = load_c64(sr, tid + r * kSegThreads - D);
+#pragma unroll
+    for (int r = 0; r < PER; ++r)
+      if (tid + r * kSegThreads < XL + 1) xl[tid + r * kSegThreads] = v[r];
   }
-  for (int i = tid; i < kNC; i += kSegThreads) tw[i] = tabs[kTabTw1024 + i];
+  lds_copy<kNC, kSegThreads>(tw, tabs + kTabTw1024, tid);
   for (int j = tid; j < NP; j += kSegThreads) {
     rt[j] = tabs[kTabRoots + j];
     hc[j] = cscale(tabs[kTabRoots + ((c * j) & (NP - 1))], win[j]);

@@ -77,6 +77,47 @@ __device__ __forceinline__ void st1_nt(float2* p, float2 a) {
   __builtin_nontemporal_store(t, reinterpret_cast<v2f_t*>(p));
 }
 
+// LDS table fills. A strided copy loop whose trip count the compiler cannot see waits for each load before
+// the next, so a thread that copies R entries pays R memory latencies before its workgroup can start. These
+// fills issue every load of a thread first, at indices clamped into range so that no load sits behind a
+// branch, and only then write LDS.
+//
+// dst[i] = src[i * STRIDE] for 0 <= i < N, by NT threads.
+template <int N, int NT, int STRIDE = 1>
+__device__ __forceinline__ void lds_copy(float2* dst, const float2* __restrict__ src, int tid) {
+  constexpr int PER = (N + NT - 1) / NT;
+  float2 v[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) v[r] = src[min(tid + r * NT, N - 1) * STRIDE];
+#pragma unroll
+  for (int r = 0; r < PER; ++r)
+    if (N % NT == 0 || tid + r * NT < N) dst[tid + r * NT] = v[r];
+}
+
+// omega_N^a for 0 <= a < N from the two-level table: rlo[e] = omega_N^e and tw[e] = omega_1024^e (e < 1024),
+// omega_N^a = omega_N^{a mod 1024} omega_1024^{(a / 1024) 1024 / M2}, with hishift = log2(1024 / M2).
+__device__ __forceinline__ int rot_lo(int a) { return a & 1023; }
+__device__ __forceinline__ int rot_hi(int a, int hishift) { return ((a >> 10) << hishift) & 1023; }
+__device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
+  return cmul(rlo[rot_lo(a)], tw[rot_hi(a, hishift)]);
+}
+
+// rot[i] = omega_N^{m2 i} for i < 1024, by NT threads (NT divides 1024), loads first as in lds_copy.
+template <int NT>
+__device__ __forceinline__ void rot_fill(float2* rot, const float2* rlo, const float2* tw, int m2, int hishift,
+                                         int tid) {
+  constexpr int PER = 1024 / NT;
+  float2 lo[PER], hi[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int a = m2 * (tid + r * NT);
+    lo[r] = rlo[rot_lo(a)];
+    hi[r] = tw[rot_hi(a, hishift)];
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) rot[tid + r * NT] = cmul(lo[r], hi[r]);
+}
+
 constexpr float kC8 = 0.70710678118654752440f;   // cos(pi/4)
 constexpr float kC16 = 0.92387953251128675613f;  // cos(pi/8)
 constexpr float kS16 = 0.38268343236508977173f;  // sin(pi/8)

@@ -103,10 +103,6 @@ __global__ void mfma_weights_kernel(const float* __restrict__ win, int Np, int S
   wlo[e] = bits16(static_cast<T16>(v - static_cast<double>(h)));
 }
 
-__device__ __forceinline__ float2 rot_factor(const float2* rlo, const float2* tw, int a, int hishift) {
-  return cmul(rlo[a & 1023], tw[((a >> 10) << hishift) & 1023]);
-}
-
 template <int NP, int PREC, bool PHASE_BY_M2, bool SEL>
 __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __restrict__ x, int N, int M2,
                                                               int m2shift, const unsigned* __restrict__ xhi,
@@ -146,8 +142,8 @@ __global__ __launch_bounds__(kThreads, 2) void ssca_pass1_mfma(const float2* __r
   const auto xr = make_rsrc(x, N * 8);
   const int hishift = 10 - m2shift;
 
-  for (int i = tid; i < 1024; i += kThreads) tw[i] = tabs[kTabTw1024 + i];
-  for (int i = tid; i < NP; i += kThreads) rt[i] = tabs[kTabRoots + i];
+  lds_copy<1024, kThreads>(tw, tabs + kTabTw1024, tid);
+  lds_copy<NP, kThreads>(rt, tabs + kTabRoots, tid);
   if (tid < 16) stp[tid] = rot_factor(rlo, tabs + kTabTw1024, 64 * m2 * tid, hishift);
 
   // Sub-chunk s: frames m1 = 256 (s / NSUB) + i (i < 256), samples kJS (s % NSUB) + [0, kJS). Each thread moves
@@ -336,9 +332,9 @@ __global__ __launch_bounds__(kPairThreads, 1) void ssca_pass1_mfma_pair(
   const float2* tw_g = tabs + kTabTw1024;
   const auto xr = make_rsrc(x, N * 8);
   const int hishift = 10 - m2shift;
-  for (int i = tid; i < kSeq; i += kPairThreads) tw[i] = tw_g[4 * i];
-  for (int i = tid; i < kM1; i += kPairThreads) rot[i] = rot_factor(rlo, tw_g, m2 * i, hishift);
-  for (int i = tid; i < NP; i += kPairThreads) rt[i] = tabs[kTabRoots + i];
+  lds_copy<kSeq, kPairThreads, 4>(tw, tw_g, tid);
+  rot_fill<kPairThreads>(rot, rlo, tw_g, m2, hishift, tid);
+  lds_copy<NP, kPairThreads>(rt, tabs + kTabRoots, tid);
   __syncthreads();
 
   // Weight offsets (elements) of subset cg + sb S/2 at this lane's row and K group; K-step kappa adds 512 kappa.
