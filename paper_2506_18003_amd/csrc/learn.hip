@@ -484,7 +484,13 @@ __global__ __launch_bounds__(kInferThreads) void infer_l12_kernel(const float* _
   for (int u = 0; u < R2; ++u) w2[u] = params[L.W2 + static_cast<int64_t>(R2 * w + u) * kHidden + kInferRows1 * g + lane];
   if (w == 0) {
     float ps = 0.f;
-    for (int i = lane; i < NP; i += 64) ps += feat[i];
+    // Loads first, then the sums in the same order as a strided loop (which would wait for each load in turn).
+    constexpr int PS = (NP + 63) / 64;
+    float fv[PS];
+#pragma unroll
+    for (int r = 0; r < PS; ++r) fv[r] = (NP % 64 == 0 || lane + 64 * r < NP) ? feat[min(lane + 64 * r, NP - 1)] : 0.f;
+#pragma unroll
+    for (int r = 0; r < PS; ++r) ps += fv[r];
     ps = wave_sum(ps);
     if (lane == 0) red[0] = ps / static_cast<float>(NP);
   }
