@@ -6,6 +6,9 @@
   scalar offset would escape the check.
 * No Stage-1 form (the headline kernel, its selection form, subset pairs, the per-frame down-conversion of
   short signals, the cross forms, every Np) and no Stage-2 kernel spills registers.
+* No LDS table fill in the Stage-1, FAM and selector kernels is a loop that waits for each load before the next
+  (a strided copy loop whose trip count the compiler cannot see compiles to load, wait, LDS write per entry, so
+  a workgroup pays one memory round trip per entry before it starts). Stage 2 keeps such loops on purpose.
 """
 import os
 import re
@@ -63,3 +66,56 @@ def test_hot_kernels_do_not_spill(asm):
     assert any("pass2" in n for n in hot)
     for n in hot:
         assert sp[n] == 0, n
+
+
+def _device_asm(tmp_path_factory, name):
+    out = tmp_path_factory.mktemp("asm") / (name + ".s")
+    subprocess.run([_hipcc(), *FLAGS, "-S", "--cuda-device-only", os.path.join(CSRC, name + ".hip"), "-o", str(out)],
+                   check=True, capture_output=True)
+    return out.read_text()
+
+
+def _serial_fill_loops(asm):
+    """Kernel name -> short loops (at most 40 lines from header to back branch) whose body issues a global or
+    buffer load, then waits for every outstanding load, then writes LDS."""
+    found = {}
+    for m in re.finditer(r"^(_Z\S+):\s*(?:;.*)?$", asm, re.M):
+        end = asm.find(".Lfunc_end", m.start())
+        lines = asm[m.start():end].splitlines()
+        labels = {}
+        for k, ln in enumerate(lines):
+            lm = re.match(r"^(\.LBB\d+_\d+):", ln)
+            if lm:
+                labels[lm.group(1)] = k
+        for k, ln in enumerate(lines):
+            bm = re.search(r"s_(?:cbranch_\w+|branch)\s+(\.LBB\d+_\d+)", ln)
+            if not bm or bm.group(1) not in labels or labels[bm.group(1)] >= k or k - labels[bm.group(1)] > 40:
+                continue
+            body = "\n".join(lines[labels[bm.group(1)]:k])
+            ld = re.search(r"(?:global|buffer)_load", body)
+            wt = re.search(r"s_waitcnt vmcnt\(0\)", body[ld.end():]) if ld else None
+            if wt and "ds_write" in body[ld.end() + wt.end():]:
+                found.setdefault(m.group(1), []).append(labels[bm.group(1)])
+    return found
+
+
+def test_detector_sees_a_serial_fill_loop():
+    fake = "\n".join(["_Zfake:", ".LBB0_1:", "\tglobal_load_dwordx2 v[4:5], v[2:3], off", "\ts_waitcnt vmcnt(0)",
+                      "\tds_write_b64 v3, v[4:5]", "\ts_cbranch_execnz .LBB0_1", ".Lfunc_end0:"])
+    assert _serial_fill_loops(fake) == {"_Zfake": [1]}
+
+
+@pytest.mark.parametrize("name, kernels", [
+    ("ssca_fp32", ("ssca_pass1_fp32",)),
+    ("ssca_mfma", ("ssca_pass1_mfma",)),
+    ("fam_fp32", ("fam_chan_fp32", "fam_pair_fp32ILi16", "fam_pair_fp32ILi32", "fam_pair_fp32ILi64",
+                  "fam_pair_fp32ILi128", "fam_pair_fp32ILi256", "fam_pair_fp32ILi512", "fam_pair_fp32ILi1024")),
+    ("learn", ("seg_periodogram_kernel", "infer_l12_kernel", "infer_l3_select_kernel")),
+])
+def test_table_fills_issue_their_loads_together(request, tmp_path_factory, name, kernels):
+    # ssca_fp32 reuses the module's compile (about a minute); the others take seconds
+    asm = request.getfixturevalue("asm") if name == "ssca_fp32" else _device_asm(tmp_path_factory, name)
+    names = re.findall(r"^(_Z\S+):\s*(?:;.*)?$", asm, re.M)
+    assert all(any(k in n for n in names) for k in kernels), "a checked kernel was not compiled"
+    bad = {n: v for n, v in _serial_fill_loops(asm).items() if any(k in n for k in kernels)}
+    assert not bad, bad
