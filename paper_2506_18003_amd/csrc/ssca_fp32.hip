@@ -298,9 +298,18 @@ __device__ __forceinline__ void p2_stage(const float2* __restrict__ src, float2*
   if constexpr (!LAST) p2_stage<L, NS * R, NT, TWN>(src, dst, buf, tw, tid);
 }
 
-// Short strips (M2 <= 64) hold only 16 M2 points per 16 rows: one wave takes each block of 16 m1', a workgroup
-// takes four such blocks of one channel, and LDS holds only the M2 twiddles they use. Longer strips give each
-// block the whole workgroup and the 1024-entry table.
+// Stage 2's workgroups of one channel, in launch order w < GX (GX a multiple of 8), to their blocks. The XCDs
+// receive workgroups round robin, w = x, x + 8, ... on XCD x; giving XCD x the blocks [x GX/8, (x + 1) GX/8)
+// makes each XCD write runs of GX/8 adjacent blocks of a strip instead of single blocks 8 apart.
+template <int GX>
+__device__ __forceinline__ int xcd_run(unsigned w) {
+  static_assert(GX % 8 == 0, "a multiple of the 8 XCDs");
+  return static_cast<int>((w & 7u) * (GX / 8) + (w >> 3));
+}
+
+// For short strips (M2 <= 64) a block of 16 m1' holds only 16 M2 points, too few for a whole workgroup: one wave
+// takes each block, a workgroup takes four blocks of one channel, and LDS holds only the M2 twiddles they use.
+// Longer strips give each block the whole workgroup and the 1024-entry table.
 template <int M2>
 struct P2Shape {
   static constexpr int NT = M2 >= 128 ? kP2Threads : 64;  // threads per block of 16 m1'
@@ -318,7 +327,7 @@ __global__ __launch_bounds__(kP2Threads) void ssca_pass2_fp32(const float2* __re
   __shared__ float2 tw[Sh::TWN];
   const int tid = threadIdx.x;
   const int g = tid / Sh::NT;
-  const int mb = blockIdx.x * Sh::G + g;  // block of 16 consecutive m1'
+  const int mb = xcd_run<kM1 / 16 / Sh::G>(blockIdx.x) * Sh::G + g;  // block of 16 consecutive m1'
   if (sel && static_cast<int>(blockIdx.y) >= sel->nch) return;
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   // Stage 2 keeps plain strided table loops (one load in flight per thread): on the 32 x 32 kernel they
@@ -345,7 +354,7 @@ __global__ __launch_bounds__(kP2Threads, 2) void ssca_pass2_fp32_32x32(const flo
   __shared__ float2 buf[16 * kP2XStride];
   __shared__ float2 tw[1024];
   const int tid = threadIdx.x;
-  const int mb = blockIdx.x;  // block of 16 consecutive m1'
+  const int mb = xcd_run<kM1 / 16>(blockIdx.x);  // block of 16 consecutive m1'
   if (sel && static_cast<int>(blockIdx.y) >= sel->nch) return;
   const int k = sel ? sel->ch[blockIdx.y] : static_cast<int>(blockIdx.y);
   for (int i = tid; i < 1024; i += kP2Threads) tw[i] = tabs[kTabTw1024 + i];  // plain loop (see ssca_pass2_fp32)
