@@ -555,7 +555,7 @@ def main():
                         "peak_without_packed_fp32": VALU_PEAK_TFLOPS,
                         "frac_without_packed_fp32": round(tfs / VALU_PEAK_TFLOPS, 4)}}
 
-    # The box's own device-to-device copy rate (torch's copy of 512 MiB, read + write), beside the datasheet peak.
+    # This GPU's own device-to-device copy rate (torch's copy of 512 MiB, read + write), beside the datasheet peak.
     csrc = torch.empty(64 << 20, dtype=torch.complex64, device=dev)
     cdst = torch.empty_like(csrc)
     cdst.copy_(csrc)
